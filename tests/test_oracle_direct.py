@@ -1,0 +1,144 @@
+"""Pins of the FP64 direct stepper (oracle/direct.c) against what the
+definition of a stencil sweep fixes (paper Section 2.2): brute-force operator
+powers, exact rational arithmetic, constant and quadratic fields, periodic
+translation invariance, linearity and thread-count independence."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import bruteforce, direct
+
+
+def setup_module(_m):
+    direct.build(force=False)
+
+
+@pytest.mark.parametrize("dims,radius,periodic", [
+    ((23,), 1, False), ((23,), 2, True), ((7, 9), 1, False), ((7, 9), 2, True),
+    ((8, 6), 1, True), ((4, 5, 6), 1, False), ((5, 4, 3), 1, True),
+])
+def test_operator_power_matches_direct(dims, radius, periodic):
+    g = synthetic.rng(11)
+    k = 2 * radius + 1
+    w = g.uniform(-1, 1, size=(k,) * len(dims))
+    x = g.random(dims)
+    steps = 3
+    L = bruteforce.operator_matrix(dims, radius, w, periodic)
+    ref = np.linalg.matrix_power(L, steps) @ x.reshape(-1)
+    got = direct.run(x, w, steps, periodic=periodic).reshape(-1)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_dyadic_heat2d_is_exact():
+    # Heat-2D coefficients (0.5, 0.125) and inputs with 8 fractional bits:
+    # every intermediate fits in 53 bits, so FP64 must equal exact arithmetic.
+    g = synthetic.rng(3)
+    x = g.integers(0, 256, size=(9, 11)) / 256.0
+    w = synthetic.heat2d_coeffs()
+    for periodic in (False, True):
+        exact = bruteforce.exact_run(x, 1, w, periodic, 4)
+        got = direct.run(x, w, 4, periodic=periodic)
+        for p, v in exact.items():
+            assert Fraction(float(got[p])) == v
+
+
+def test_rounding_error_within_bound():
+    # Random FP64 data: error against exact arithmetic is within T*P*2^-53
+    # of the absolute-value sum (one rounding per multiply and per add).
+    g = synthetic.rng(4)
+    x = g.random((6, 7))
+    w = g.uniform(-1, 1, size=(3, 3))
+    steps = 3
+    exact = bruteforce.exact_run(x, 1, w, False, steps)
+    got = direct.run(x, w, steps)
+    absw = float(np.abs(w).sum())
+    bound = steps * 2 * 9 * 2.0 ** -53 * absw ** steps * float(np.abs(x).max()) * 4
+    for p, v in exact.items():
+        assert abs(float(got[p]) - float(v)) <= bound
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_constant_field(ndim):
+    # A constant field kappa maps to (sum c)^T kappa exactly (dyadic data) on a
+    # periodic grid, and at points at least T*r from a zero boundary.
+    g = synthetic.rng(5)
+    k = 3
+    w = g.integers(-8, 9, size=(k,) * ndim) / 16.0
+    kappa = 0.75
+    dims = {1: (40,), 2: (12, 13), 3: (9, 8, 10)}[ndim]
+    x = np.full(dims, kappa)
+    steps = 3
+    want = float(w.sum()) ** steps * kappa
+    per = direct.run(x, w, steps, periodic=True)
+    assert np.all(per == want)
+    zer = direct.run(x, w, steps, periodic=False)
+    inner = tuple(slice(steps, n - steps) for n in dims)
+    assert np.all(zer[inner] == want)
+
+
+def quad_field(ny, nx, a, b, c, d, e, h):
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                       indexing="ij")
+    return a * x * x + b * x * y + c * y * y + d * x + e * y + h
+
+
+def test_laplacian_of_quadratic_is_exact():
+    # 5-point Laplacian of a x^2 + b xy + c y^2 + d x + e y + h is 2a + 2c
+    # exactly at interior points.
+    lap = np.array([[0, 1, 0], [1, -4, 1], [0, 1, 0]], dtype=np.float64)
+    a, b, c, d, e, h = 3, -2, 5, 7, -1, 4
+    f = quad_field(12, 14, a, b, c, d, e, h)
+    got = direct.run(f, lap, 1)
+    assert np.all(got[1:-1, 1:-1] == 2 * a + 2 * c)
+
+
+def test_heat2d_of_quadratic_is_exact():
+    # Heat-2D = identity + Laplacian / 8, so it maps f to f + (2a+2c)/8.
+    a, b, c, d, e, h = 1, 2, 3, -4, 5, -6
+    f = quad_field(10, 12, a, b, c, d, e, h)
+    got = direct.run(f, synthetic.heat2d_coeffs(), 1)
+    assert np.all(got[1:-1, 1:-1] == f[1:-1, 1:-1] + 0.125 * (2 * a + 2 * c))
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_periodic_translation_invariance(ndim):
+    g = synthetic.rng(6)
+    dims = {1: (31,), 2: (9, 10), 3: (6, 7, 5)}[ndim]
+    w = g.uniform(-1, 1, size=(5,) * ndim)
+    x = g.random(dims)
+    shift = tuple(range(1, ndim + 1))
+    axes = tuple(range(ndim))
+    a = np.roll(direct.run(x, w, 2, periodic=True), shift, axis=axes)
+    b = direct.run(np.roll(x, shift, axis=axes), w, 2, periodic=True)
+    assert np.array_equal(a, b)
+
+
+def test_linearity():
+    g = synthetic.rng(7)
+    w = g.uniform(-1, 1, size=(3, 3))
+    x, y = g.random((10, 9)), g.random((10, 9))
+    lhs = direct.run(2.0 * x + y, w, 3)
+    rhs = 2.0 * direct.run(x, w, 3) + direct.run(y, w, 3)
+    assert np.max(np.abs(lhs - rhs)) <= 1e-13
+
+
+def test_thread_count_does_not_change_result():
+    g = synthetic.rng(8)
+    w = g.uniform(-1, 1, size=(3, 3, 3))
+    x = g.random((12, 11, 10))
+    a = direct.run(x, w, 2, nthreads=1)
+    b = direct.run(x, w, 2, nthreads=4)
+    assert np.array_equal(a, b)
+
+
+def test_star_is_box_with_zeros():
+    # A star stencil is the box stencil with zeros off the axes.
+    mask = synthetic.stencil_mask("star", 2, 2)
+    assert mask.sum() == 9
+    g = synthetic.rng(9)
+    w = np.where(mask, g.uniform(-1, 1, size=mask.shape), 0.0)
+    x = g.random((9, 8))
+    L = bruteforce.operator_matrix((9, 8), 2, w, False)
+    assert np.max(np.abs(direct.run(x, w, 1).reshape(-1) - L @ x.reshape(-1))) < 1e-14
