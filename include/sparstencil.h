@@ -1,0 +1,172 @@
+/*
+ * sparstencil -- stencil sweeps on gfx950 recast as 2:4-structured-sparse
+ * matrix products (SparStencil, arXiv 2506.22969).
+ *
+ * C ABI of libsparstencil.so.  Every entry point takes plain host values and
+ * host or device pointers, never throws, and reports failures through its
+ * return code.  Device pointers are HIP device allocations on the current
+ * device; `stream` arguments are hipStream_t values passed as void* (NULL =
+ * the null stream).
+ *
+ * The operation: a fixed-coefficient stencil applied T times to a 1-, 2- or
+ * 3-D grid (paper Section 2.2, with the commented Box-2D9P pseudo-code that
+ * writes each sweep to a second mesh and swaps the meshes).  Sweep:
+ *     out[p] = sum over the (2r+1)^d box offsets o of  w[o] * in~[p - r + o]
+ * (correlation orientation), where in~ is `in` inside the grid and 0 outside
+ * it (zero halo) or `in` at the index taken modulo the grid size (periodic).
+ *
+ * Grids are dense, row-major, slowest dimension first.  Split-state grids
+ * (SS_SPLIT_BF16) hold two planes back to back: [hi (N values) | lo (N)],
+ * value = hi + lo.
+ */
+#ifndef SPARSTENCIL_H
+#define SPARSTENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SS_OK = 0,
+    SS_PENDING = 1,          /* poll: job admitted or queued, not finished   */
+    SS_E_INVALID = -1,       /* bad argument (null, size, shape, coeffs)     */
+    SS_E_UNSUPPORTED = -2,   /* valid request no engine here implements      */
+    SS_E_NOMEM = -3,         /* device or arena memory exhausted             */
+    SS_E_DEVICE = -4,        /* a HIP call failed                            */
+    SS_E_NOT_FOUND = -5,     /* unknown job id                               */
+    SS_E_BUSY = -6           /* resource in use (e.g. job table full)        */
+} ss_status;
+
+typedef enum { SS_SHAPE_BOX = 0, SS_SHAPE_STAR = 1 } ss_shape;
+
+/* State storage and arithmetic of a plan. */
+typedef enum {
+    SS_F64 = 0,            /* FP64 state, FP64 arithmetic                        */
+    SS_F32 = 1,            /* FP32 state, FP32 arithmetic (direct engine)        */
+    SS_F16 = 2,            /* binary16 state, single-part binary16 products      */
+    SS_F32_SPLIT_F16 = 3,  /* FP32 state; state and coefficients split into
+                              binary16 hi + lo parts, products hi*hi + hi*lo +
+                              lo*hi accumulated in FP32                         */
+    SS_F32_SPLIT_BF16 = 4, /* as above with bfloat16 parts                       */
+    SS_SPLIT_BF16 = 5      /* state stored as bfloat16 hi and lo planes          */
+} ss_dtype;
+
+typedef enum { SS_BC_ZERO = 0, SS_BC_PERIODIC = 1 } ss_boundary;
+
+typedef enum {
+    SS_ENGINE_AUTO = 0,    /* sparse MFMA where the plan supports it             */
+    SS_ENGINE_SMFMAC = 1,  /* 2:4 sparse MFMA on the permuted staircase matrix   */
+    SS_ENGINE_MFMA = 2,    /* dense MFMA on the unpermuted staircase matrix      */
+    SS_ENGINE_DIRECT = 3   /* direct neighbour sum on the vector ALUs            */
+} ss_engine;
+
+typedef struct {
+    uint32_t struct_size;  /* sizeof(ss_plan_opts)                               */
+    int32_t boundary;      /* ss_boundary                                        */
+    int32_t fuse_steps;    /* S >= 1 sweeps composed into one (periodic only)    */
+    int32_t r1, r2;        /* tile width (x) and height (y); 0,0 = explore       */
+    int32_t engine;        /* ss_engine                                          */
+    uint32_t flags;        /* SS_FLAG_* bits, 0 by default                       */
+} ss_plan_opts;
+
+/* Build the host tables only: no device is touched, and run / sweep reject
+ * the plan.  Lets tools and CPU tests read back plans without a GPU. */
+#define SS_FLAG_HOST_ONLY 1u
+
+typedef struct ss_plan_ *ss_plan_t;
+
+/*
+ * Build a plan (paper Sections 3.1-3.3: layout morphing, structured sparsity
+ * conversion by Algorithm 1, layout exploration, metadata and lookup tables)
+ * and upload its tables to the current device.
+ *
+ *   shape      SS_SHAPE_BOX or SS_SHAPE_STAR; a star's coefficients must be 0
+ *              off the axes
+ *   radius     r >= 1
+ *   coeffs     host, (2r+1)^ndim FP64 values, row-major, slowest dim first
+ *   ndim       1, 2 or 3
+ *   grid_dims  host, ndim sizes (slowest first), each >= 1
+ *   dtype      ss_dtype
+ *   opts       NULL for defaults (zero halo, S = 1, explore, auto engine)
+ *
+ * On success *out owns host and device tables until sparstencil_plan_destroy.
+ * A plan is immutable and may be shared by threads.  Errors: SS_E_INVALID,
+ * SS_E_UNSUPPORTED (e.g. no engine for the dtype/engine pair, S > 1 with a
+ * zero halo, |coefficient| beyond the binary16 range), SS_E_NOMEM, SS_E_DEVICE.
+ */
+ss_status sparstencil_plan(ss_plan_t *out, int32_t shape, int32_t radius, const double *coeffs,
+                           int32_t ndim, const int64_t *grid_dims, int32_t dtype,
+                           const ss_plan_opts *opts);
+
+/* Plan read-back (for tests and tools).  Size protocol: with buf == NULL,
+ * *nbytes receives the size; otherwise *nbytes must be >= the size and the
+ * table is copied to host memory buf.  SS_E_INVALID for an unknown `what`. */
+enum {
+    SS_Q_INFO = 0,        /* ss_plan_info                                        */
+    SS_Q_COEFFS = 1,      /* double[kf^ndim]: the (composed) coefficients used   */
+    SS_Q_PERM = 2,        /* int32[K_pad]: A' column per K slot, -1 = zero col   */
+    SS_Q_VALUES = 3,      /* double[m'][K_pad/2]: compressed A'' values          */
+    SS_Q_META = 4,        /* uint8[m'][K_pad/4][2]: positions (i0 < i1)          */
+    SS_Q_HI = 5,          /* uint16[m'][K_pad/2]: hi parts (bit patterns)        */
+    SS_Q_LO = 6,          /* uint16[m'][K_pad/2]: lo parts, scaled by sigma      */
+    SS_Q_LUT = 7,         /* int32[K_pad][3]: (pz, pr, pc), -1s for zero cols    */
+    SS_Q_MODEL = 8,       /* double[n][7]: r1, r2, T, T_compute, T_global,
+                             T_shared, K_pad for every candidate layout          */
+    SS_Q_KERNEL_LUT = 9   /* int32[n]: LDS offsets the launched kernel gathers   */
+};
+
+typedef struct {
+    int32_t ndim, radius, k;          /* k = 2*radius_fused + 1               */
+    int32_t fuse_steps;
+    int32_t r1, r2, m_b, g, planes;
+    int32_t m_prime, k_prime, k_pad, zeros;
+    int32_t engine;                   /* engine actually used                 */
+    int32_t dtype, boundary;
+    int32_t passes;                   /* MMA passes per product (3 = split)   */
+    int32_t launches_per_sweep;       /* kernel launches per (fused) sweep    */
+    double sigma;                     /* lo-part scale (2^11 for binary16)    */
+    double plan_seconds;              /* host time spent in sparstencil_plan  */
+    int64_t dims[3];
+} ss_plan_info;
+
+ss_status sparstencil_plan_query(ss_plan_t plan, int32_t what, void *buf, size_t *nbytes);
+
+/* Release a plan's host and device tables.  The caller must have finished
+ * (synchronised) every run that uses it.  NULL is accepted. */
+ss_status sparstencil_plan_destroy(ss_plan_t plan);
+
+/*
+ * Apply `steps` sweeps: the result is left in `out`.  Asynchronous on
+ * `stream`; returns after enqueueing.
+ *   in, out  device grids of the plan's dims and dtype (split: 2 planes);
+ *            they must not overlap.  `in` serves as the second mesh of the
+ *            ping-pong, so its contents are unspecified afterwards.
+ *   steps    >= 0; 0 copies in to out.  With fuse_steps S > 1, floor(steps/S)
+ *            fused launches run, then steps mod S unfused ones.
+ * Errors: SS_E_INVALID (null, in == out, steps < 0), SS_E_DEVICE (launch).
+ */
+ss_status sparstencil_run(ss_plan_t plan, void *in, void *out, int64_t steps, void *stream);
+
+/*
+ * One (fused) sweep from `in` to `out` (no copy, no remainder handling): the
+ * building block `run` repeats.  Same argument rules as sparstencil_run.
+ */
+ss_status sparstencil_sweep(ss_plan_t plan, const void *in, void *out, void *stream);
+
+/* Number of sweep kernels `run` launches for `steps` sweeps (0 for a copy);
+ * an even count is preceded by one device-to-device copy of the grid. */
+int64_t sparstencil_launch_count(ss_plan_t plan, int64_t steps);
+
+/* Bytes of one grid buffer of the plan (all planes). */
+size_t sparstencil_grid_bytes(ss_plan_t plan);
+
+const char *sparstencil_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPARSTENCIL_H */

@@ -1,0 +1,554 @@
+// C ABI of libsparstencil: plan construction (host tables + device upload),
+// sweeps, runs and read-back.  See include/sparstencil.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sparstencil.h"
+#include "kargs.hpp"
+#include "planner.hpp"
+
+using namespace ss;
+
+struct ss_plan_ {
+    ss_plan_info info{};
+    int ndim = 2;
+    int64_t dims[3] = {1, 1, 1};
+    int dtype = 0, boundary = 0, engine = 0, fuse = 1;
+    int k = 3, rad = 1;               // of the (composed) stencil the kernels apply
+    std::vector<double> w;            // (composed) coefficients, k^ndim
+    // canonical tables
+    std::vector<int32_t> perm;
+    std::vector<double> values;
+    std::vector<uint8_t> meta;
+    std::vector<uint16_t> hi, lo;
+    std::vector<int32_t> lut;
+    std::vector<double> model;        // rows of 7
+    std::vector<int32_t> kernel_lut;
+    // device
+    void *dev = nullptr;
+    MmaArgs margs{};
+    MmaLaunch mma = nullptr;
+    DirectArgs dargs{};
+    int device = 0;
+    bool host_only = false;
+    ss_plan_ *rem = nullptr;          // unfused plan for leftover sweeps
+};
+
+namespace {
+
+const int64_t kMaxDim = (int64_t)1 << 30;
+
+size_t state_bytes(int dtype) {
+    switch (dtype) {
+        case SS_F64: return 8;
+        case SS_F32: case SS_F32_SPLIT_F16: case SS_F32_SPLIT_BF16: return 4;
+        case SS_F16: return 2;
+        case SS_SPLIT_BF16: return 4;  // two 2-byte planes
+        default: return 0;
+    }
+}
+
+int64_t points(const ss_plan_ *p) { return p->dims[0] * p->dims[1] * p->dims[2]; }
+
+bool valid_star(const std::vector<double> &w, int ndim, int r) {
+    const int k = 2 * r + 1;
+    const int nz = ndim == 3 ? k : 1, ny = ndim >= 2 ? k : 1;
+    for (int a = 0; a < nz; ++a)
+        for (int b = 0; b < ny; ++b)
+            for (int c = 0; c < k; ++c) {
+                int off = 0;
+                if (ndim == 3 && a != r) ++off;
+                if (ndim >= 2 && b != r) ++off;
+                if (c != r) ++off;
+                if (off > 1 && w[((size_t)a * ny + b) * k + c] != 0.0) return false;
+            }
+    return true;
+}
+
+// Fill the 2-D MMA kernel tables.  Sparse: compressed A'' in the SMFMAC
+// operand layout with its index words; dense: A' in natural column order.
+// Gather offsets are in u16 units from the tile's slab base.
+ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, int kc_count,
+                           int pitch, int F, int S, std::vector<uint8_t> *blob, size_t *off_hi,
+                           size_t *off_lo, size_t *off_idx, size_t *off_boff) {
+    const int MB = gm.m_prime() / 16;
+    const std::vector<double> amat = morph_matrix(gm, p->w);
+    const int kp = gm.k_prime();
+    auto split = [&](double c, uint16_t *h, uint16_t *l) -> bool {
+        if (part == kPartF16) {
+            if (!to_f16_bits(c, h)) return false;
+            return to_f16_bits((c - f16_value(*h)) * 2048.0, l);
+        }
+        if (!to_bf16_bits(c, h)) return false;
+        return to_bf16_bits(c - bf16_value(*h), l);
+    };
+    const int VPK = mode == kSparse ? 8 : 4;
+    std::vector<uint16_t> ahi((size_t)MB * kc_count * 64 * 8), alo(ahi.size());
+    std::vector<uint32_t> aidx((size_t)MB * kc_count * 64, 0);
+    std::vector<int32_t> boff((size_t)kc_count * 4 * VPK, 0);
+    if (mode == kSparse) {
+        const int groups = (int)p->perm.size() / 4;
+        for (int mb = 0; mb < MB; ++mb)
+            for (int kc = 0; kc < kc_count; ++kc)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = mb * 16 + (l & 15), qa = l >> 4;
+                    uint32_t word = 0;
+                    for (int ea = 0; ea < 8; ++ea) {
+                        const int gl = ea >> 1, s = ea & 1;
+                        const int qb = 2 * (qa & 1) + (gl >> 1);
+                        const int m = 2 * (qa >> 1) + (gl & 1);
+                        const int j = kc * 16 + 4 * qb + m;     // canonical 4-group
+                        const size_t vi = ((size_t)row * groups + j) * 2 + s;
+                        const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + ea;
+                        ahi[t] = p->hi[vi];
+                        alo[t] = p->lo[vi];
+                        word |= (uint32_t)p->meta[vi] << (2 * ea);
+                    }
+                    aidx[((size_t)mb * kc_count + kc) * 64 + l] = word;
+                }
+    } else {
+        for (int mb = 0; mb < MB; ++mb)
+            for (int kc = 0; kc < kc_count; ++kc)
+                for (int l = 0; l < 64; ++l)
+                    for (int e = 0; e < 8; ++e) {
+                        const int row = mb * 16 + (l & 15);
+                        const int col = kc * 32 + 8 * (l >> 4) + e;
+                        const double c = col < kp ? amat[(size_t)row * kp + col] : 0.0;
+                        uint16_t h, lw;
+                        if (!split(c, &h, &lw)) return SS_E_UNSUPPORTED;
+                        const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + e;
+                        ahi[t] = h;
+                        alo[t] = lw;
+                    }
+    }
+    // gather offsets: K slot pair (kk, kk+1) of B register v of lane group qb
+    for (int kc = 0; kc < kc_count; ++kc)
+        for (int qb = 0; qb < 4; ++qb)
+            for (int v = 0; v < VPK; ++v) {
+                const int kk = mode == kSparse ? kc * 64 + 16 * qb + 2 * v : kc * 32 + 8 * qb + 2 * v;
+                int col = mode == kSparse ? p->perm[kk] : (kk < kp ? kk : kZeta);
+                int32_t o = 0;
+                if (col != kZeta) {
+                    const int pr = (col % (gm.m_b * gm.g)) / gm.g, pc = col % gm.g;
+                    const int j = pc / 2;
+                    o = pr * pitch + 4 * ((j % F) * S + j / F);
+                }
+                boff[((size_t)kc * 4 + qb) * VPK + v] = o;
+            }
+    // pack: a_hi | a_lo | a_idx | boff, each 256-byte aligned
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    *off_hi = 0;
+    *off_lo = align(*off_hi + ahi.size() * 2);
+    *off_idx = align(*off_lo + alo.size() * 2);
+    *off_boff = align(*off_idx + aidx.size() * 4);
+    blob->assign(align(*off_boff + boff.size() * 4), 0);
+    std::memcpy(blob->data() + *off_hi, ahi.data(), ahi.size() * 2);
+    std::memcpy(blob->data() + *off_lo, alo.data(), alo.size() * 2);
+    std::memcpy(blob->data() + *off_idx, aidx.data(), aidx.size() * 4);
+    std::memcpy(blob->data() + *off_boff, boff.data(), boff.size() * 4);
+    p->kernel_lut = boff;
+    return SS_OK;
+}
+
+// Canonical tables of the sparse layout: perm, compressed values, metadata,
+// hi/lo parts, gather LUT.
+ss_status build_canonical(ss_plan_ *p, const Geometry &gm, int part, int kfrag) {
+    const std::vector<double> amat = morph_matrix(gm, p->w);
+    const PairList pl = matrix_pairs(gm);
+    std::vector<int> perm = group_pairs(pl, kfrag);
+    Compressed cm;
+    if (!compress(gm, amat, perm, &cm)) return SS_E_UNSUPPORTED;
+    p->perm.assign(perm.begin(), perm.end());
+    p->values = cm.values;
+    p->meta = cm.meta;
+    p->hi.resize(cm.values.size());
+    p->lo.resize(cm.values.size());
+    for (size_t i = 0; i < cm.values.size(); ++i) {
+        const double c = cm.values[i];
+        bool ok;
+        if (part == kPartF16) {
+            ok = to_f16_bits(c, &p->hi[i]) && to_f16_bits((c - f16_value(p->hi[i])) * 2048.0, &p->lo[i]);
+        } else {
+            ok = to_bf16_bits(c, &p->hi[i]) && to_bf16_bits(c - bf16_value(p->hi[i]), &p->lo[i]);
+        }
+        if (!ok) return SS_E_UNSUPPORTED;
+    }
+    p->lut.assign(perm.size() * 3, -1);
+    const int plane = gm.m_b * gm.g;
+    for (size_t kk = 0; kk < perm.size(); ++kk) {
+        const int c = perm[kk];
+        if (c == kZeta) continue;
+        p->lut[kk * 3 + 0] = c / plane;
+        p->lut[kk * 3 + 1] = (c % plane) / gm.g;
+        p->lut[kk * 3 + 2] = c % gm.g;
+    }
+    p->info.zeros = pl.zeros;
+    return SS_OK;
+}
+
+ss_status upload(ss_plan_ *p, const std::vector<uint8_t> &blob) {
+    if (p->host_only) return SS_OK;
+    if (hipGetDevice(&p->device) != hipSuccess) return SS_E_DEVICE;
+    if (blob.empty()) return SS_OK;
+    if (hipMalloc(&p->dev, blob.size()) != hipSuccess) {
+        p->dev = nullptr;
+        return SS_E_NOMEM;
+    }
+    if (hipMemcpy(p->dev, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) return SS_E_DEVICE;
+    return SS_OK;
+}
+
+struct Candidate {
+    int r1, r2;
+};
+
+const Candidate kCandidates2d[] = {{8, 8}, {16, 4}};
+
+ss_status plan_mma2d(ss_plan_ *p, int engine) {
+    const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
+    const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    const int kfrag = mode == kSparse ? 64 : 32;
+    ModelParams mp{};
+    mp.ndim = p->ndim;
+    mp.k = p->k;
+    for (int d = 0; d < 3; ++d) mp.dims[d] = d < p->ndim ? p->dims[3 - p->ndim + d] : 1;
+    mp.elem_bytes = 4;
+    mp.coef_bytes = 2;
+    mp.passes = 3;
+    mp.planes_state = 1;
+    mp.kfrag = 64;
+    // candidates this build has kernels for
+    std::vector<Candidate> cands;
+    for (const Candidate &c : kCandidates2d) {
+        if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
+        const Geometry gm = make_geometry(2, p->k, c.r1, c.r2);
+        int kc;
+        if (mode == kSparse) {
+            const std::vector<int> perm = group_pairs(matrix_pairs(gm), 64);
+            if (!pair_aligned(gm, perm)) continue;
+            kc = (int)perm.size() / 64;
+        } else {
+            if (gm.g % 2) continue;
+            kc = (gm.k_prime() + 31) / 32;
+        }
+        if (!find_mma2d(MmaKey{c.r1, c.r2, kc, p->rad, mode, part})) continue;
+        cands.push_back(c);
+    }
+    if (cands.empty()) return SS_E_UNSUPPORTED;
+    ModelRow best{};
+    bool have = false;
+    p->model.clear();
+    for (const Candidate &c : cands) {
+        const ModelRow r = model_time(mp, c.r1, c.r2);
+        const double row[7] = {(double)r.r1, (double)r.r2, r.t, r.t_compute, r.t_global, r.t_shared,
+                               (double)r.k_pad};
+        p->model.insert(p->model.end(), row, row + 7);
+        if (!have || model_better(r, best)) {
+            best = r;
+            have = true;
+        }
+    }
+    const Geometry gm = make_geometry(2, p->k, best.r1, best.r2);
+    ss_status st = build_canonical(p, gm, part, 64);
+    if (st != SS_OK) return st;
+    if (mode == kDense) {
+        // the dense engine consumes A' in natural column order
+        p->perm.clear();
+        const int kd = (gm.k_prime() + 31) / 32 * 32;
+        for (int c = 0; c < kd; ++c) p->perm.push_back(c < gm.k_prime() ? c : kZeta);
+    }
+    const int kc = mode == kSparse ? (int)p->perm.size() / 64 : (int)p->perm.size() / 32;
+    const MmaKey key{best.r1, best.r2, kc, p->rad, mode, part};
+    int wgh, pitch, F, S;
+    if (!mma2d_geometry(key, &wgh, &pitch, &F, &S)) return SS_E_UNSUPPORTED;
+    std::vector<uint8_t> blob;
+    size_t o_hi, o_lo, o_idx, o_boff;
+    st = build_mma_tables(p, gm, mode, part, kc, pitch, F, S, &blob, &o_hi, &o_lo, &o_idx, &o_boff);
+    if (st != SS_OK) return st;
+    st = upload(p, blob);
+    if (st != SS_OK) return st;
+    char *d = static_cast<char *>(p->dev);
+    p->mma = find_mma2d(key);
+    p->margs.ny = (int)p->dims[1];
+    p->margs.nx = (int)p->dims[2];
+    p->margs.periodic = p->boundary == SS_BC_PERIODIC;
+    p->margs.inv_sigma = part == kPartF16 ? 1.0f / 2048.0f : 1.0f;
+    p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
+    p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
+    p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
+    p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
+    p->engine = engine;
+    p->info.r1 = gm.r1;
+    p->info.r2 = gm.r2;
+    p->info.m_b = gm.m_b;
+    p->info.g = gm.g;
+    p->info.planes = gm.planes;
+    p->info.m_prime = gm.m_prime();
+    p->info.k_prime = gm.k_prime();
+    p->info.k_pad = (int)p->perm.size();
+    p->info.passes = 3;
+    p->info.sigma = part == kPartF16 ? 2048.0 : 1.0;
+    return SS_OK;
+}
+
+ss_status plan_direct(ss_plan_ *p) {
+    const bool f64 = p->dtype == SS_F64;
+    std::vector<uint8_t> blob(p->w.size() * (f64 ? 8 : 4));
+    if (f64) {
+        std::memcpy(blob.data(), p->w.data(), blob.size());
+    } else {
+        std::vector<float> wf(p->w.begin(), p->w.end());
+        std::memcpy(blob.data(), wf.data(), blob.size());
+    }
+    ss_status st = upload(p, blob);
+    if (st != SS_OK) return st;
+    p->dargs.nz = (int)p->dims[0];
+    p->dargs.ny = (int)p->dims[1];
+    p->dargs.nx = (int)p->dims[2];
+    p->dargs.rz = p->ndim == 3 ? p->rad : 0;
+    p->dargs.ry = p->ndim >= 2 ? p->rad : 0;
+    p->dargs.rx = p->rad;
+    p->dargs.periodic = p->boundary == SS_BC_PERIODIC;
+    p->dargs.w = p->dev;
+    p->engine = SS_ENGINE_DIRECT;
+    p->info.passes = 1;
+    p->info.sigma = 1.0;
+    return SS_OK;
+}
+
+void free_plan(ss_plan_ *p) {
+    if (!p) return;
+    free_plan(p->rem);
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+}
+
+ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs, int ndim,
+                    const int64_t *grid_dims, int dtype, const ss_plan_opts *opts, bool allow_fuse) {
+    if (!out || !coeffs || !grid_dims) return SS_E_INVALID;
+    if (shape != SS_SHAPE_BOX && shape != SS_SHAPE_STAR) return SS_E_INVALID;
+    if (ndim < 1 || ndim > 3 || radius < 1 || radius > 16) return SS_E_INVALID;
+    if (state_bytes(dtype) == 0) return SS_E_INVALID;
+    ss_plan_opts o{sizeof(ss_plan_opts), SS_BC_ZERO, 1, 0, 0, SS_ENGINE_AUTO, 0};
+    if (opts) {
+        if (opts->struct_size < sizeof(ss_plan_opts)) return SS_E_INVALID;
+        o = *opts;
+    }
+    if (o.boundary != SS_BC_ZERO && o.boundary != SS_BC_PERIODIC) return SS_E_INVALID;
+    if (o.fuse_steps < 1 || o.fuse_steps > 8) return SS_E_INVALID;
+    if (o.engine < SS_ENGINE_AUTO || o.engine > SS_ENGINE_DIRECT) return SS_E_INVALID;
+    if ((o.r1 == 0) != (o.r2 == 0) || o.r1 < 0 || o.r2 < 0) return SS_E_INVALID;
+    if (o.fuse_steps > 1 && o.boundary != SS_BC_PERIODIC) return SS_E_UNSUPPORTED;
+    if (o.fuse_steps > 1 && !allow_fuse) return SS_E_INVALID;
+    if (o.flags & ~SS_FLAG_HOST_ONLY) return SS_E_INVALID;
+
+    auto t0 = std::chrono::steady_clock::now();
+    ss_plan_ *p = new (std::nothrow) ss_plan_();
+    if (!p) return SS_E_NOMEM;
+    p->ndim = ndim;
+    for (int d = 0; d < ndim; ++d) {
+        if (grid_dims[d] < 1 || grid_dims[d] > kMaxDim) {
+            delete p;
+            return SS_E_INVALID;
+        }
+        p->dims[3 - ndim + d] = grid_dims[d];
+    }
+    p->dtype = dtype;
+    p->host_only = (o.flags & SS_FLAG_HOST_ONLY) != 0;
+    p->boundary = o.boundary;
+    p->fuse = o.fuse_steps;
+    const int k0 = 2 * radius + 1;
+    size_t nw = 1;
+    for (int d = 0; d < ndim; ++d) nw *= (size_t)k0;
+    std::vector<double> w(coeffs, coeffs + nw);
+    for (double c : w)
+        if (!std::isfinite(c)) {
+            delete p;
+            return SS_E_INVALID;
+        }
+    if (shape == SS_SHAPE_STAR && !valid_star(w, ndim, radius)) {
+        delete p;
+        return SS_E_INVALID;
+    }
+    int kf = k0;
+    p->w = o.fuse_steps > 1 ? compose(w, ndim, k0, o.fuse_steps, &kf) : w;
+    p->k = kf;
+    p->rad = (kf - 1) / 2;
+    // a periodic grid must be at least as wide as the composed stencil
+    if (o.boundary == SS_BC_PERIODIC)
+        for (int d = 3 - ndim; d < 3; ++d)
+            if (p->dims[d] < p->rad) {
+                delete p;
+                return SS_E_UNSUPPORTED;
+            }
+    p->info.r1 = o.r1;
+    p->info.r2 = o.r2;
+
+    ss_status st = SS_E_UNSUPPORTED;
+    const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16;
+    int engine = o.engine;
+    if (split && ndim == 2 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
+        st = plan_mma2d(p, SS_ENGINE_SMFMAC);
+        if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma2d(p, SS_ENGINE_MFMA);
+    } else if (split && ndim == 2 && engine == SS_ENGINE_MFMA) {
+        st = plan_mma2d(p, SS_ENGINE_MFMA);
+    }
+    if (st != SS_OK && (engine == SS_ENGINE_DIRECT || engine == SS_ENGINE_AUTO) &&
+        (dtype == SS_F32 || dtype == SS_F64 || split) && o.r1 == 0)
+        st = plan_direct(p);
+    if (st != SS_OK) {
+        free_plan(p);
+        return st;
+    }
+    if (o.fuse_steps > 1) {
+        ss_plan_opts ro = o;
+        ro.fuse_steps = 1;
+        ro.r1 = ro.r2 = 0;
+        ro.engine = p->engine;
+        st = make_plan(&p->rem, shape, radius, coeffs, ndim, grid_dims, dtype, &ro, false);
+        if (st != SS_OK) {
+            free_plan(p);
+            return st;
+        }
+    }
+    ss_plan_info &inf = p->info;
+    inf.ndim = ndim;
+    inf.radius = p->rad;
+    inf.k = p->k;
+    inf.fuse_steps = p->fuse;
+    inf.engine = p->engine;
+    inf.dtype = dtype;
+    inf.boundary = p->boundary;
+    inf.launches_per_sweep = 1;
+    for (int d = 0; d < 3; ++d) inf.dims[d] = p->dims[d];
+    inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    return SS_OK;
+}
+
+hipError_t sweep(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {
+    if (p->engine == SS_ENGINE_DIRECT) {
+        DirectArgs a = p->dargs;
+        a.in = in;
+        a.out = out;
+        return launch_direct(a, p->dtype == SS_F64, s);
+    }
+    MmaArgs a = p->margs;
+    a.in = static_cast<const float *>(in);
+    a.out = static_cast<float *>(out);
+    return p->mma(a, s);
+}
+
+template <class T>
+ss_status copy_out(const std::vector<T> &v, void *buf, size_t *nbytes) {
+    const size_t need = v.size() * sizeof(T);
+    if (!nbytes) return SS_E_INVALID;
+    if (!buf) {
+        *nbytes = need;
+        return SS_OK;
+    }
+    if (*nbytes < need) return SS_E_INVALID;
+    if (need) std::memcpy(buf, v.data(), need);
+    *nbytes = need;
+    return SS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ss_status sparstencil_plan(ss_plan_t *out, int32_t shape, int32_t radius, const double *coeffs, int32_t ndim,
+                           const int64_t *grid_dims, int32_t dtype, const ss_plan_opts *opts) {
+    if (out) *out = nullptr;
+    try {
+        return make_plan(out, shape, radius, coeffs, ndim, grid_dims, dtype, opts, true);
+    } catch (...) {
+        return SS_E_NOMEM;
+    }
+}
+
+ss_status sparstencil_plan_destroy(ss_plan_t plan) {
+    free_plan(plan);
+    return SS_OK;
+}
+
+size_t sparstencil_grid_bytes(ss_plan_t p) {
+    if (!p) return 0;
+    return (size_t)points(p) * state_bytes(p->dtype);
+}
+
+int64_t sparstencil_launch_count(ss_plan_t p, int64_t steps) {
+    if (!p || steps <= 0) return 0;
+    return steps / p->fuse + steps % p->fuse;
+}
+
+ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void *stream) {
+    if (!p || !in || !out || in == out || steps < 0 || p->host_only) return SS_E_INVALID;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t bytes = sparstencil_grid_bytes(p);
+    if (steps == 0)
+        return hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess ? SS_OK : SS_E_DEVICE;
+    const int64_t fused = steps / p->fuse, rest = steps % p->fuse;
+    const int64_t total = fused + rest;
+    // Ping-pong between the two meshes so that the last sweep writes `out`;
+    // with an even number of sweeps the input is first copied into `out`.
+    void *src = in, *dst = out;
+    if (total % 2 == 0) {
+        if (hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SS_E_DEVICE;
+        src = out;
+        dst = in;
+    }
+    for (int64_t i = 0; i < total; ++i) {
+        const ss_plan_ *q = i < fused ? p : p->rem;
+        if (sweep(q, src, dst, s) != hipSuccess) return SS_E_DEVICE;
+        std::swap(src, dst);
+    }
+    return SS_OK;
+}
+
+ss_status sparstencil_sweep(ss_plan_t p, const void *in, void *out, void *stream) {
+    if (!p || !in || !out || in == out || p->host_only) return SS_E_INVALID;
+    return sweep(p, in, out, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK : SS_E_DEVICE;
+}
+
+ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *nbytes) {
+    if (!p || !nbytes) return SS_E_INVALID;
+    switch (what) {
+        case SS_Q_INFO: {
+            std::vector<ss_plan_info> v{p->info};
+            return copy_out(v, buf, nbytes);
+        }
+        case SS_Q_COEFFS: return copy_out(p->w, buf, nbytes);
+        case SS_Q_PERM: return copy_out(p->perm, buf, nbytes);
+        case SS_Q_VALUES: return copy_out(p->values, buf, nbytes);
+        case SS_Q_META: return copy_out(p->meta, buf, nbytes);
+        case SS_Q_HI: return copy_out(p->hi, buf, nbytes);
+        case SS_Q_LO: return copy_out(p->lo, buf, nbytes);
+        case SS_Q_LUT: return copy_out(p->lut, buf, nbytes);
+        case SS_Q_MODEL: return copy_out(p->model, buf, nbytes);
+        case SS_Q_KERNEL_LUT: return copy_out(p->kernel_lut, buf, nbytes);
+        default: return SS_E_INVALID;
+    }
+}
+
+const char *sparstencil_status_string(int32_t s) {
+    switch (s) {
+        case SS_OK: return "ok";
+        case SS_PENDING: return "pending";
+        case SS_E_INVALID: return "invalid argument";
+        case SS_E_UNSUPPORTED: return "unsupported";
+        case SS_E_NOMEM: return "out of memory";
+        case SS_E_DEVICE: return "device error";
+        case SS_E_NOT_FOUND: return "not found";
+        case SS_E_BUSY: return "busy";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

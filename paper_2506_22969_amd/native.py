@@ -1,0 +1,227 @@
+"""ctypes binding of libsparstencil.so (argument marshalling only).
+
+Every function here forwards to the C entry point of the same name in
+include/sparstencil.h; all stencil work runs in the library's HIP kernels.
+Device buffers are passed as integer addresses or as objects with a
+``data_ptr()`` method (torch tensors); streams as integer hipStream_t handles
+(``torch.cuda.current_stream().cuda_stream``) or None for the null stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsparstencil.so")
+
+SS_OK, SS_PENDING = 0, 1
+SS_E_INVALID, SS_E_UNSUPPORTED, SS_E_NOMEM, SS_E_DEVICE, SS_E_NOT_FOUND, SS_E_BUSY = -1, -2, -3, -4, -5, -6
+SHAPES = {"box": 0, "star": 1}
+DTYPES = {"f64": 0, "f32": 1, "f16": 2, "f32_split_f16": 3, "f32_split_bf16": 4, "split_bf16": 5}
+BOUNDARIES = {"zero": 0, "periodic": 1}
+ENGINES = {"auto": 0, "smfmac": 1, "mfma": 2, "direct": 3}
+ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
+(Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT) = range(10)
+
+EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
+           "sparstencil_sweep", "sparstencil_launch_count", "sparstencil_grid_bytes",
+           "sparstencil_status_string"]
+
+
+class SparStencilError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("boundary", ctypes.c_int32),
+                ("fuse_steps", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
+                ("engine", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("radius", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("fuse_steps", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
+                ("m_b", ctypes.c_int32), ("g", ctypes.c_int32), ("planes", ctypes.c_int32),
+                ("m_prime", ctypes.c_int32), ("k_prime", ctypes.c_int32), ("k_pad", ctypes.c_int32),
+                ("zeros", ctypes.c_int32), ("engine", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("boundary", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("launches_per_sweep", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double), ("dims", ctypes.c_int64 * 3)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "dims"}
+        d["dims"] = tuple(self.dims)
+        d["engine_name"] = ENGINE_NAMES.get(self.engine, "?")
+        return d
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python paper_2506_22969_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.sparstencil_plan.restype = i32
+        L.sparstencil_plan.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(ctypes.c_double), i32,
+                                       ctypes.POINTER(i64), i32, ctypes.POINTER(PlanOpts)]
+        L.sparstencil_plan_query.restype = i32
+        L.sparstencil_plan_query.argtypes = [vp, i32, vp, ctypes.POINTER(sz)]
+        L.sparstencil_plan_destroy.restype = i32
+        L.sparstencil_plan_destroy.argtypes = [vp]
+        L.sparstencil_run.restype = i32
+        L.sparstencil_run.argtypes = [vp, vp, vp, i64, vp]
+        L.sparstencil_sweep.restype = i32
+        L.sparstencil_sweep.argtypes = [vp, vp, vp, vp]
+        L.sparstencil_launch_count.restype = i64
+        L.sparstencil_launch_count.argtypes = [vp, i64]
+        L.sparstencil_grid_bytes.restype = sz
+        L.sparstencil_grid_bytes.argtypes = [vp]
+        L.sparstencil_status_string.restype = ctypes.c_char_p
+        L.sparstencil_status_string.argtypes = [i32]
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x)
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise SparStencilError(status, what)
+    return status
+
+
+def status_string(status: int) -> str:
+    return lib().sparstencil_status_string(int(status)).decode()
+
+
+# ----------------------------------------------------------------------------
+# the C entry points
+
+def sparstencil_plan(shape, radius, coeffs, ndim, grid_dims, dtype, opts=None) -> int:
+    """Returns the plan handle (int).  shape/dtype may be names or ints."""
+    shape = SHAPES.get(shape, shape)
+    dtype = DTYPES.get(dtype, dtype)
+    w = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(-1))
+    dims = (ctypes.c_int64 * int(ndim))(*[int(d) for d in grid_dims])
+    h = ctypes.c_void_p()
+    popts = ctypes.byref(opts) if opts is not None else None
+    st = lib().sparstencil_plan(ctypes.byref(h), int(shape), int(radius),
+                                w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(ndim), dims,
+                                int(dtype), popts)
+    _check(st, "sparstencil_plan")
+    return int(h.value)
+
+
+def sparstencil_plan_query(plan: int, what: int) -> bytes:
+    n = ctypes.c_size_t(0)
+    _check(lib().sparstencil_plan_query(plan, what, None, ctypes.byref(n)), "sparstencil_plan_query")
+    buf = ctypes.create_string_buffer(max(1, n.value))
+    _check(lib().sparstencil_plan_query(plan, what, buf, ctypes.byref(n)), "sparstencil_plan_query")
+    return buf.raw[: n.value]
+
+
+def sparstencil_plan_destroy(plan: int) -> None:
+    _check(lib().sparstencil_plan_destroy(plan), "sparstencil_plan_destroy")
+
+
+def sparstencil_run(plan: int, inp, out, steps: int, stream=None) -> None:
+    _check(lib().sparstencil_run(plan, _ptr(inp), _ptr(out), int(steps), _ptr(stream)), "sparstencil_run")
+
+
+def sparstencil_sweep(plan: int, inp, out, stream=None) -> None:
+    _check(lib().sparstencil_sweep(plan, _ptr(inp), _ptr(out), _ptr(stream)), "sparstencil_sweep")
+
+
+def sparstencil_launch_count(plan: int, steps: int) -> int:
+    return int(lib().sparstencil_launch_count(plan, int(steps)))
+
+
+def sparstencil_grid_bytes(plan: int) -> int:
+    return int(lib().sparstencil_grid_bytes(plan))
+
+
+def sparstencil_status_string(status: int) -> str:
+    return status_string(status)
+
+
+# ----------------------------------------------------------------------------
+# convenience wrapper
+
+FLAG_HOST_ONLY = 1
+
+
+def make_opts(boundary="zero", fuse_steps=1, r1=0, r2=0, engine="auto", flags=0) -> PlanOpts:
+    return PlanOpts(ctypes.sizeof(PlanOpts), BOUNDARIES.get(boundary, boundary), int(fuse_steps),
+                    int(r1), int(r2), ENGINES.get(engine, engine), int(flags))
+
+
+class Plan:
+    """Owns one plan handle; see sparstencil_plan for the arguments."""
+
+    def __init__(self, shape, radius, coeffs, grid_dims, dtype, boundary="zero", fuse_steps=1,
+                 r1=0, r2=0, engine="auto", host_only=False):
+        grid_dims = tuple(int(d) for d in grid_dims)
+        self.grid_dims = grid_dims
+        self.dtype = dtype
+        self.handle = 0
+        self.handle = sparstencil_plan(shape, radius, coeffs, len(grid_dims), grid_dims, dtype,
+                                       make_opts(boundary, fuse_steps, r1, r2, engine,
+                                                 FLAG_HOST_ONLY if host_only else 0))
+
+    def close(self):
+        if getattr(self, "handle", 0):
+            sparstencil_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def info(self) -> dict:
+        raw = sparstencil_plan_query(self.handle, Q_INFO)
+        return PlanInfo.from_buffer_copy(raw).as_dict()
+
+    def table(self, what: int) -> np.ndarray:
+        raw = sparstencil_plan_query(self.handle, what)
+        dt = {Q_COEFFS: np.float64, Q_PERM: np.int32, Q_VALUES: np.float64, Q_META: np.uint8,
+              Q_HI: np.uint16, Q_LO: np.uint16, Q_LUT: np.int32, Q_MODEL: np.float64,
+              Q_KERNEL_LUT: np.int32}[what]
+        return np.frombuffer(raw, dtype=dt).copy()
+
+    def run(self, inp, out, steps, stream=None):
+        sparstencil_run(self.handle, inp, out, steps, stream)
+
+    def sweep(self, inp, out, stream=None):
+        sparstencil_sweep(self.handle, inp, out, stream)
+
+    def launch_count(self, steps):
+        return sparstencil_launch_count(self.handle, steps)
+
+    @property
+    def grid_bytes(self) -> int:
+        return sparstencil_grid_bytes(self.handle)

@@ -1,0 +1,178 @@
+"""GPU parity: libsparstencil's HIP engines against the FP64 oracle, through
+the C ABI, on seeded synthetic grids.
+
+Tolerances (normwise relative error after T sweeps): each
+split-precision sweep is bounded by split_step_bound(fmt, n_mma) * sum|c|
+relative to the largest state value; the tests allow T times that bound.
+The direct FP32 engine gets T * (P + 1) * 2^-24 * sum|c|, FP64 1e-13.
+"""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import direct as oracle_direct
+
+from .helpers import cone_sample, normwise_err, sample_points, split_step_bound
+
+torch = pytest.importorskip("torch")
+native = pytest.importorskip("paper_2506_22969_amd.native")
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def run_plan(plan, x0: np.ndarray, steps: int) -> np.ndarray:
+    a = torch.from_numpy(np.ascontiguousarray(x0)).to(DEV)
+    b = torch.empty_like(a)
+    plan.run(a, b, steps, stream())
+    torch.cuda.synchronize()
+    return b.cpu().numpy()
+
+
+def n_mma_of(info) -> int:
+    # MMAs accumulating into one output: 3 passes per 64-wide (sparse) or
+    # 32-wide (dense) K chunk
+    chunk = 64 if info["engine_name"] == "smfmac" else 32
+    return 3 * info["k_pad"] // chunk
+
+
+def tol_for(info, w, steps, dtype):
+    s = float(np.abs(w).sum())
+    if info["engine_name"] == "direct":
+        p = np.count_nonzero(w)
+        return steps * (p + 1) * 2.0 ** -24 * s * 2
+    fmt = "f16" if dtype == "f32_split_f16" else "bf16"
+    return steps * split_step_bound(fmt, n_mma_of(info)) * s
+
+
+SMALL = [(200, 300), (64, 128), (129, 131), (7, 5), (1, 200), (300, 1), (256, 256)]
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
+@pytest.mark.parametrize("dims", SMALL)
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_box9_f16_split_small(engine, dims, boundary):
+    w, seed = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
+    x0 = synthetic.grid_f32(dims, seed=0)
+    steps = 5
+    with native.Plan("box", 1, w, dims, "f32_split_f16", boundary=boundary, engine=engine) as p:
+        info = p.info
+        assert info["engine_name"] == engine
+        got = run_plan(p, x0, steps)
+    ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=(boundary == "periodic"))
+    err = normwise_err(got, ref)
+    tol = tol_for(info, w, steps, "f32_split_f16")
+    print(f"engine={engine} dims={dims} bc={boundary} err={err:.3e} tol={tol:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma"])
+@pytest.mark.parametrize("r1,r2", [(8, 8), (16, 4)])
+def test_bf16_split_and_tiles(engine, r1, r2):
+    dims = (333, 517)
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=3, grid_shape=dims)
+    x0 = synthetic.grid_f32(dims, seed=4)
+    steps = 6
+    for dtype in ("f32_split_f16", "f32_split_bf16"):
+        with native.Plan("box", 1, w, dims, dtype, engine=engine, r1=r1, r2=r2) as p:
+            info = p.info
+            assert (info["r1"], info["r2"]) == (r1, r2)
+            got = run_plan(p, x0, steps)
+        ref = oracle_direct.run(x0.astype(np.float64), w, steps)
+        err = normwise_err(got, ref)
+        tol = tol_for(info, w, steps, dtype)
+        print(f"{engine} ({r1},{r2}) {dtype} err={err:.3e} tol={tol:.3e}")
+        assert err <= tol
+
+
+def test_star5_heat2d_f64_direct_c1():
+    # Heat-2D Jacobi, 256x256 FP64, zero halo, 10 sweeps.
+    w = synthetic.heat2d_coeffs()
+    x0 = synthetic.grid_f64((256, 256), seed=0)
+    with native.Plan("star", 1, w, (256, 256), "f64") as p:
+        got = run_plan(p, x0, 10)
+    ref = oracle_direct.run(x0, w, 10)
+    assert normwise_err(got, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
+def test_constant_field_bit_exact(engine):
+    # Heat-2D coefficients and the state 0.75 are binary16 numbers; every
+    # product and partial sum is exact, so interior points equal (sum c)^T k.
+    w = synthetic.heat2d_coeffs()
+    dims = (96, 160)
+    x0 = np.full(dims, 0.75, dtype=np.float32)
+    steps = 3
+    with native.Plan("star", 1, w, dims, "f32_split_f16", engine=engine) as p:
+        got = run_plan(p, x0, steps)
+    assert np.all(got[steps:-steps, steps:-steps] == 0.75)
+    with native.Plan("star", 1, w, dims, "f32_split_f16", engine=engine, boundary="periodic") as p:
+        got = run_plan(p, x0, steps)
+    assert np.all(got == 0.75)
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma"])
+def test_laplacian_of_quadratic_bit_exact(engine):
+    # 5-point Laplacian of a x^2 + b xy + c y^2 + d x + e y + h is 2a + 2c at
+    # interior points; integer inputs below 2048 are exact binary16 values.
+    lap = np.array([[0, 1, 0], [1, -4, 1], [0, 1, 0]], dtype=np.float64)
+    ny, nx = 40, 44
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    a, b, c, d, e, h = 1, -1, 1, 2, -3, 5
+    f = a * x * x + b * x * y + c * y * y + d * x + e * y + h
+    assert np.abs(f).max() < 2048
+    with native.Plan("star", 1, lap, (ny, nx), "f32_split_f16", engine=engine) as p:
+        got = run_plan(p, f.astype(np.float32), 1)
+    assert np.all(got[1:-1, 1:-1] == 2 * a + 2 * c)
+
+
+def test_steps_zero_one_two_and_determinism():
+    dims = (100, 140)
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
+    x0 = synthetic.grid_f32(dims, seed=7)
+    with native.Plan("box", 1, w, dims, "f32_split_f16") as p:
+        assert np.array_equal(run_plan(p, x0, 0), x0)
+        one = run_plan(p, x0, 1)
+        two = run_plan(p, x0, 2)
+        again = run_plan(p, x0, 2)
+        assert p.launch_count(2) == 2
+    assert np.array_equal(two, again)
+    # two sweeps equal one sweep applied twice, bit for bit
+    with native.Plan("box", 1, w, dims, "f32_split_f16") as p:
+        twice = run_plan(p, one, 1)
+    assert np.array_equal(two, twice)
+
+
+def test_run_rejects_aliasing():
+    dims = (64, 64)
+    w = synthetic.heat2d_coeffs()
+    with native.Plan("star", 1, w, dims, "f32_split_f16") as p:
+        a = torch.zeros(dims, device=DEV)
+        with pytest.raises(native.SparStencilError):
+            p.run(a, a, 1, stream())
+
+
+def test_box9_full_size_sampled():
+    # The benchmark's workload: Box-2D9P on 10240^2, FP32 state, binary16
+    # split on the sparse engine, 100 sweeps, zero halo; checked at sampled
+    # points through their dependency cones.
+    dims = (10240, 10240)
+    steps = 100
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
+    x0 = synthetic.grid_f32(dims, seed=0)
+    with native.Plan("box", 1, w, dims, "f32_split_f16") as p:
+        info = p.info
+        assert info["engine_name"] == "smfmac"
+        got = run_plan(p, x0, steps)
+    pts = sample_points(*dims, 24, seed=1)
+    ref = cone_sample(x0, w, steps, pts)
+    vals = np.array([got[y, x] for (y, x) in pts], dtype=np.float64)
+    err = float(np.abs(vals - ref).max() / np.abs(ref).max())
+    tol = tol_for(info, w, steps, "f32_split_f16")
+    print(f"full-size sampled err={err:.3e} tol={tol:.3e}")
+    assert err <= tol

@@ -1,0 +1,95 @@
+"""Plan tables of libsparstencil (host-only plans, no GPU) against the oracle's
+independent re-derivation: permutation, compressed values, metadata, hi/lo
+parts and gather LUT must match bit for bit; the layout-exploration model must
+give the same times and the same argmin (Section 3.3, Eqs. 6-11)."""
+import numpy as np
+import pytest
+
+import synthetic
+from oracle import tables as T
+
+native = pytest.importorskip("paper_2506_22969_amd.native")
+
+
+def host_plan(shape, radius, w, dims, dtype="f32_split_f16", **kw):
+    return native.Plan(shape, radius, w, dims, dtype, host_only=True, engine="smfmac", **kw)
+
+
+CASES = [
+    ("box", 1, 2, (10240, 10240), 8, 8),
+    ("box", 1, 2, (10240, 10240), 16, 4),
+    ("star", 1, 2, (4096, 4096), 8, 8),
+    ("box", 1, 2, (300, 257), 0, 0),
+]
+
+
+@pytest.mark.parametrize("shape,radius,ndim,dims,r1,r2", CASES)
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_tables_bit_exact(shape, radius, ndim, dims, r1, r2, fmt):
+    w, _ = synthetic.random_coeffs(shape, radius, ndim, seed=5, grid_shape=dims)
+    dtype = "f32_split_f16" if fmt == "f16" else "f32_split_bf16"
+    with host_plan(shape, radius, w, dims, dtype, r1=r1, r2=r2) as p:
+        info = p.info
+        assert info["engine_name"] == "smfmac"
+        a, s, d = T.morph(T.bounding_box(shape, radius, ndim, w), info["r1"], info["r2"])
+        assert (info["m_prime"], info["k_prime"]) == (d.m_prime, d.k_prime)
+        pairs, zeros = T.plane_pairs(d)
+        perm = T.group(pairs, 64)
+        assert info["zeros"] == zeros
+        assert info["k_pad"] == len(perm)
+        assert np.array_equal(p.table(native.Q_PERM), np.array(perm, dtype=np.int32))
+        vals, meta = T.compress(a, s, perm)
+        assert np.array_equal(p.table(native.Q_VALUES), vals.reshape(-1))
+        assert np.array_equal(p.table(native.Q_META), meta.reshape(-1).astype(np.uint8))
+        hi, lo = T.split_hilo(vals, fmt)
+        assert np.array_equal(p.table(native.Q_HI), hi.reshape(-1))
+        assert np.array_equal(p.table(native.Q_LO), lo.reshape(-1))
+        lut = T.gather_lut(d, perm)
+        assert np.array_equal(p.table(native.Q_LUT), lut.reshape(-1).astype(np.int32))
+
+
+@pytest.mark.parametrize("dims", [(10240, 10240), (1024, 1024), (64, 200)])
+def test_model_and_argmin_match_oracle(dims):
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=5, grid_shape=dims)
+    with host_plan("box", 1, w, dims) as p:
+        rows = p.table(native.Q_MODEL).reshape(-1, 7)
+        info = p.info
+    cands = [(int(r[0]), int(r[1])) for r in rows]
+    best, table = T.explore(3, 2, dims, cands, elem_bytes=4, coef_bytes=2, passes=3, planes_state=1)
+    for r in rows:
+        t, tc, tg, ts, kpad = table[(int(r[0]), int(r[1]))]
+        assert r[2] == pytest.approx(t, rel=1e-12)
+        assert r[3] == pytest.approx(tc, rel=1e-12)
+        assert r[4] == pytest.approx(tg, rel=1e-12)
+        assert r[5] == pytest.approx(ts, rel=1e-12)
+        assert int(r[6]) == kpad
+    assert (info["r1"], info["r2"]) == best
+
+
+def test_heat2d_coefficients_split_exactly():
+    # 0.5 and 0.125 are binary16 numbers: every lo part is zero.
+    w = synthetic.heat2d_coeffs()
+    with host_plan("star", 1, w, (256, 256)) as p:
+        assert np.all(p.table(native.Q_LO) == 0)
+
+
+def test_fused_plan_uses_composed_coefficients():
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=5)
+    with native.Plan("box", 1, w, (512, 512), "f32", boundary="periodic", fuse_steps=2,
+                     engine="direct", host_only=True) as p:
+        c = p.table(native.Q_COEFFS).reshape(5, 5)
+        assert p.info["k"] == 5
+    assert np.array_equal(c, T.compose(w, 2))
+
+
+def test_invalid_arguments():
+    w = synthetic.heat2d_coeffs()
+    with pytest.raises(native.SparStencilError):
+        native.Plan("star", 1, np.ones((3, 3)), (64, 64), "f32_split_f16", host_only=True)  # star off-axis
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w, (0, 64), "f32_split_f16", host_only=True)
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w, (64, 64), "f32", fuse_steps=2, host_only=True)  # fusion needs periodic
+    big = w * 1e6
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, big, (64, 64), "f32_split_f16", engine="smfmac", host_only=True)
