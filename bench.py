@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep-loop", type=int, default=40, help="sweeps timed for the roofline")
+    ap.add_argument("--serve-jobs", type=int, default=200,
+                    help="jobs of the serving-mix leg (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the measured batch capacity")
     return ap.parse_args()
 
 
@@ -130,6 +134,102 @@ def cpu_baseline(x0: np.ndarray, w: np.ndarray, gpu_out: np.ndarray, budget_s: f
                       f"error check on 16 sampled outputs of the 100-sweep run via dependency cones"}, err
 
 
+SERVE_DTYPES = {"f32": "f32_split_f16", "split_bf16": "f32_split_bf16"}
+
+
+def serving_leg(native, torch, n_jobs: int, load: float):
+    """Serving mix: jobs of several stencils, sizes, step counts and dtypes
+    through one server.  Three passes over the same jobs: all submitted at
+    once (batch capacity), one job at a time through sparstencil_run, and
+    Poisson arrivals at `load` x the batch capacity (latency percentiles from
+    arrival to result)."""
+    import synthetic
+
+    jobs = synthetic.job_stream(n_jobs, rate_per_s=1.0)
+    dev = "cuda:0"
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(0)
+    plans, inputs, sinks, coeffs = {}, {}, {}, {}
+    for j in jobs:
+        key = (j["kind"], j["grid"], j["dtype"], j["coeff_seed"])
+        if key not in plans:
+            # every grid of the mix exceeds the stability check's per-axis
+            # lattice cap, so one draw per (stencil, seed) serves all sizes
+            ck = (j["kind"], j["coeff_seed"])
+            if ck not in coeffs:
+                coeffs[ck] = synthetic.random_coeffs(j["shape"], j["radius"], j["ndim"], seed=j["coeff_seed"],
+                                                     grid_shape=j["grid"])[0]
+            plans[key] = native.Plan(j["shape"], j["radius"], coeffs[ck], j["grid"], SERVE_DTYPES[j["dtype"]])
+        if j["grid"] not in inputs:
+            inputs[j["grid"]] = torch.rand(j["grid"], generator=gen, device=dev, dtype=torch.float32)
+            sinks[j["grid"]] = torch.empty_like(inputs[j["grid"]])
+        j["plan"] = plans[key]
+        j["points"] = int(np.prod(j["grid"]))
+    total_ps = sum(j["points"] * j["steps"] for j in jobs)
+    largest = max(p.grid_bytes for p in plans.values())
+    arena_bytes = max(16 << 30, 4 * largest)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def batch(srv):
+        t0 = srv.clock()
+        ids = [srv.submit(j["plan"], inputs[j["grid"]], sinks[j["grid"]], j["steps"]) for j in jobs]
+        srv.drain()
+        return srv.clock() - t0, ids
+
+    with native.Server(arena, arena_bytes, max_jobs=n_jobs, num_streams=4) as srv:
+        batch(srv)  # warm-up: first launches of every kernel variant
+        makespan, _ = batch(srv)
+        capacity = n_jobs / makespan
+        rate = load * capacity
+        arrivals = synthetic.job_stream(n_jobs, rate_per_s=rate)
+        ids = []
+        t0 = time.perf_counter()
+        for j, a in zip(jobs, arrivals):
+            wait = a["arrival"] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(j["plan"], inputs[j["grid"]], sinks[j["grid"]], j["steps"]))
+        srv.drain()
+        lat = []
+        for jid in ids:
+            st, info = srv.poll(jid)
+            if st != native.SS_OK:
+                raise RuntimeError(f"serving job failed: {native.status_string(st)}")
+            lat.append((info["t_done"] - info["t_submit"]) * 1e3)
+        open_span = time.perf_counter() - t0
+
+    # one job at a time through sparstencil_run on one stream
+    stream = torch.cuda.current_stream()
+    scratch = {g: torch.empty_like(x) for g, x in inputs.items()}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in jobs:
+        a = scratch[j["grid"]]
+        a.copy_(inputs[j["grid"]])
+        j["plan"].run(a, sinks[j["grid"]], j["steps"], stream.cuda_stream)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    lat = np.array(lat)
+    return {
+        "jobs": n_jobs,
+        "mix": "Poisson stream over 1D 5-point 2^20, 2D 5/9/13-point 1024^2-8192^2, 3D 7/27-point "
+               "128^3-384^3, steps U{10..200}, FP32 state with binary16 or bfloat16 split products, "
+               "4 coefficient seeds per stencil",
+        "point_steps": total_ps,
+        "batch_gstencil_s": round(total_ps / makespan / 1e9, 2),
+        "one_at_a_time_gstencil_s": round(total_ps / seq / 1e9, 2),
+        "capacity_jobs_s": round(capacity, 2),
+        "load": load,
+        "open_loop_gstencil_s": round(total_ps / open_span / 1e9, 2),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "arena_gib": round(arena_bytes / 2 ** 30, 2),
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -189,6 +289,10 @@ def main():
         "engines": results,
         "roofline": roof,
     }
+    if args.serve_jobs > 0:
+        del x0_dev
+        torch.cuda.empty_cache()
+        line["serving"] = serving_leg(native, torch, args.serve_jobs, args.serve_load)
     if not args.no_cpu:
         cb, err = cpu_baseline(x0, w, gpu_out, args.cpu_seconds)
         line["cpu_baseline"] = cb

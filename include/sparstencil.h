@@ -165,6 +165,74 @@ size_t sparstencil_grid_bytes(ss_plan_t plan);
 
 const char *sparstencil_status_string(int32_t status);
 
+/*
+ * Serving loop (not part of the paper's method, which runs one grid at a
+ * time: a batching layer around the sweep of Section 3.4).  A server owns a
+ * worker thread that admits submitted jobs first-come first-served while the
+ * caller's device arena has room for a job's two buffers, then advances every
+ * admitted job by one (fused) sweep per round.  Jobs whose plans have equal
+ * device tables (same stencil, coefficients, dtype, boundary, fusion and
+ * tile) are swept by one multi-grid launch per round, up to 16 grids; other
+ * plan classes go to the server's other streams so their launches overlap.
+ * A job's result is bit-identical to sparstencil_run of its plan.
+ */
+typedef struct ss_server_ *ss_server_t;
+
+typedef struct {
+    uint64_t id;
+    int32_t state;         /* 0 queued, 1 running, 2 done, 3 failed             */
+    int32_t status;        /* SS_OK, or the error that failed the job           */
+    int64_t steps_total;   /* sweeps requested                                  */
+    int64_t steps_done;    /* sweeps applied so far                             */
+    double t_submit;       /* seconds on the server clock (sparstencil_server_clock) */
+    double t_admit;        /* admitted into the arena (0 while queued)          */
+    double t_done;         /* result copied to `out` (0 until then)             */
+} ss_job_info;
+
+/*
+ * Create a server on the current device.
+ *   arena        device memory the server sub-allocates job buffers from; the
+ *                caller keeps ownership and frees it after destroy.
+ *   arena_bytes  size of the arena.
+ *   max_jobs     bound on queued + running jobs (submit returns SS_E_BUSY).
+ *   num_streams  1..16 streams for concurrent plan classes.
+ * Errors: SS_E_INVALID, SS_E_NOMEM, SS_E_DEVICE.
+ */
+ss_status sparstencil_server_create(ss_server_t *out, void *arena, size_t arena_bytes, int32_t max_jobs,
+                                    int32_t num_streams);
+
+/*
+ * Queue `steps` (>= 1) sweeps of `plan` on the grid at `in`; the result is
+ * written to `out` when the job finishes.  in and out may be host or device
+ * memory and must stay valid, like the plan, until the job is done; `in` is
+ * copied into the arena on admission and not modified.  *job_id receives the
+ * job's id.  Errors: SS_E_INVALID (null, steps < 1, host-only plan, server
+ * shutting down), SS_E_NOMEM (two grid buffers exceed the whole arena),
+ * SS_E_BUSY (max_jobs reached).
+ */
+ss_status sparstencil_submit(ss_server_t server, ss_plan_t plan, const void *in, void *out, int64_t steps,
+                             uint64_t *job_id);
+
+/*
+ * State of a job: SS_PENDING while queued or running, SS_OK when its result
+ * is in `out`, the job's error if it failed, SS_E_NOT_FOUND for an unknown or
+ * released id.  `info` (may be null) receives a snapshot.
+ */
+ss_status sparstencil_poll(ss_server_t server, uint64_t job_id, ss_job_info *info);
+
+/* Forget a finished job's record (SS_E_BUSY while it is pending). */
+ss_status sparstencil_job_release(ss_server_t server, uint64_t job_id);
+
+/* Block until no job is queued or running. */
+ss_status sparstencil_server_drain(ss_server_t server);
+
+/* Seconds since the server was created (the clock of ss_job_info times). */
+double sparstencil_server_clock(ss_server_t server);
+
+/* Finish every queued and running job, then stop the worker and free the
+ * server (not the arena).  A null server is a no-op. */
+ss_status sparstencil_server_destroy(ss_server_t server);
+
 #ifdef __cplusplus
 }
 #endif

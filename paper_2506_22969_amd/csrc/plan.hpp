@@ -1,0 +1,46 @@
+// Plan object behind ss_plan_t (internal to the library).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/sparstencil.h"
+#include "kargs.hpp"
+
+struct ss_plan_ {
+    ss_plan_info info{};
+    int ndim = 2;
+    int64_t dims[3] = {1, 1, 1};      // slowest first; leading 1s for 1-D / 2-D
+    int dtype = 0, boundary = 0, engine = 0, fuse = 1;
+    int k = 3, rad = 1;               // of the (composed) stencil the kernels apply
+    std::vector<double> w;            // (composed) coefficients, k^ndim
+    // canonical tables
+    std::vector<int32_t> perm;
+    std::vector<double> values;
+    std::vector<uint8_t> meta;
+    std::vector<uint16_t> hi, lo;
+    std::vector<int32_t> lut;
+    std::vector<double> model;        // rows of 7
+    std::vector<int32_t> kernel_lut;
+    // device
+    void *dev = nullptr;
+    ss::MmaArgs margs{};
+    ss::MmaLaunch mma = nullptr;
+    ss::DirectArgs dargs{};
+    int device = 0;
+    bool host_only = false;
+    uint64_t klass = 0;               // equal for plans with identical device tables
+    ss_plan_ *rem = nullptr;          // unfused plan for leftover sweeps
+};
+
+namespace ss {
+
+// One sweep over n grids (n <= kMaxJobs) of plans of p's class: one launch.
+hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
+                       const int64_t (*dims)[3], hipStream_t s);
+hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s);
+size_t plan_state_bytes(const ss_plan_ *p);
+// True when a and b can share one launch: equal device tables and kernel.
+bool same_class(const ss_plan_ *a, const ss_plan_ *b);
+
+}  // namespace ss

@@ -11,34 +11,10 @@
 
 #include "../../include/sparstencil.h"
 #include "kargs.hpp"
+#include "plan.hpp"
 #include "planner.hpp"
 
 using namespace ss;
-
-struct ss_plan_ {
-    ss_plan_info info{};
-    int ndim = 2;
-    int64_t dims[3] = {1, 1, 1};
-    int dtype = 0, boundary = 0, engine = 0, fuse = 1;
-    int k = 3, rad = 1;               // of the (composed) stencil the kernels apply
-    std::vector<double> w;            // (composed) coefficients, k^ndim
-    // canonical tables
-    std::vector<int32_t> perm;
-    std::vector<double> values;
-    std::vector<uint8_t> meta;
-    std::vector<uint16_t> hi, lo;
-    std::vector<int32_t> lut;
-    std::vector<double> model;        // rows of 7
-    std::vector<int32_t> kernel_lut;
-    // device
-    void *dev = nullptr;
-    MmaArgs margs{};
-    MmaLaunch mma = nullptr;
-    DirectArgs dargs{};
-    int device = 0;
-    bool host_only = false;
-    ss_plan_ *rem = nullptr;          // unfused plan for leftover sweeps
-};
 
 namespace {
 
@@ -73,10 +49,10 @@ bool valid_star(const std::vector<double> &w, int ndim, int r) {
 
 // Fill the 2-D MMA kernel tables.  Sparse: compressed A'' in the SMFMAC
 // operand layout with its index words; dense: A' in natural column order.
-// Gather offsets are in u16 units from the tile's slab base.
+// Gather offsets are in floats from the tile's patch origin in the slab.
 ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, int kc_count,
-                           int pitch, int F, int S, std::vector<uint8_t> *blob, size_t *off_hi,
-                           size_t *off_lo, size_t *off_idx, size_t *off_boff) {
+                           int cpitch, std::vector<uint8_t> *blob, size_t *off_hi,
+                           size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
     const int MB = gm.m_prime() / 16;
     const std::vector<double> amat = morph_matrix(gm, p->w);
     const int kp = gm.k_prime();
@@ -136,18 +112,18 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, 
                 int32_t o = 0;
                 if (col != kZeta) {
                     const int pr = (col % (gm.m_b * gm.g)) / gm.g, pc = col % gm.g;
-                    const int j = pc / 2;
-                    o = pr * pitch + 4 * ((j % F) * S + j / F);
+                    o = pr * cpitch + pc;
                 }
                 boff[((size_t)kc * 4 + qb) * VPK + v] = o;
             }
-    // pack: a_hi | a_lo | a_idx | boff, each 256-byte aligned
+    // pack: a_hi | a_lo | a_idx | boff | 1 KiB of zeros, each 256-byte aligned
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     *off_hi = 0;
     *off_lo = align(*off_hi + ahi.size() * 2);
     *off_idx = align(*off_lo + alo.size() * 2);
     *off_boff = align(*off_idx + aidx.size() * 4);
-    blob->assign(align(*off_boff + boff.size() * 4), 0);
+    *off_zero = align(*off_boff + boff.size() * 4);
+    blob->assign(*off_zero + 1024, 0);
     std::memcpy(blob->data() + *off_hi, ahi.data(), ahi.size() * 2);
     std::memcpy(blob->data() + *off_lo, alo.data(), alo.size() * 2);
     std::memcpy(blob->data() + *off_idx, aidx.data(), aidx.size() * 4);
@@ -265,24 +241,23 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     }
     const int kc = mode == kSparse ? (int)p->perm.size() / 64 : (int)p->perm.size() / 32;
     const MmaKey key{best.r1, best.r2, kc, p->rad, mode, part};
-    int wgh, pitch, F, S;
-    if (!mma2d_geometry(key, &wgh, &pitch, &F, &S)) return SS_E_UNSUPPORTED;
+    int wgh, cpitch;
+    if (!mma2d_geometry(key, &wgh, &cpitch)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
-    size_t o_hi, o_lo, o_idx, o_boff;
-    st = build_mma_tables(p, gm, mode, part, kc, pitch, F, S, &blob, &o_hi, &o_lo, &o_idx, &o_boff);
+    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    st = build_mma_tables(p, gm, mode, part, kc, cpitch, &blob, &o_hi, &o_lo, &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
     st = upload(p, blob);
     if (st != SS_OK) return st;
     char *d = static_cast<char *>(p->dev);
     p->mma = find_mma2d(key);
-    p->margs.ny = (int)p->dims[1];
-    p->margs.nx = (int)p->dims[2];
     p->margs.periodic = p->boundary == SS_BC_PERIODIC;
     p->margs.inv_sigma = part == kPartF16 ? 1.0f / 2048.0f : 1.0f;
     p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
     p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
     p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
     p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
+    p->margs.zeros = reinterpret_cast<const float *>(d + o_zero);
     p->engine = engine;
     p->info.r1 = gm.r1;
     p->info.r2 = gm.r2;
@@ -308,9 +283,6 @@ ss_status plan_direct(ss_plan_ *p) {
     }
     ss_status st = upload(p, blob);
     if (st != SS_OK) return st;
-    p->dargs.nz = (int)p->dims[0];
-    p->dargs.ny = (int)p->dims[1];
-    p->dargs.nx = (int)p->dims[2];
     p->dargs.rz = p->ndim == 3 ? p->rad : 0;
     p->dargs.ry = p->ndim >= 2 ? p->rad : 0;
     p->dargs.rx = p->rad;
@@ -427,22 +399,20 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     inf.boundary = p->boundary;
     inf.launches_per_sweep = 1;
     for (int d = 0; d < 3; ++d) inf.dims[d] = p->dims[d];
+    // plans with the same class share device-table contents: their grids can
+    // be swept by one launch
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](const void *d, size_t n) {
+        const unsigned char *c = static_cast<const unsigned char *>(d);
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    const int32_t key[8] = {p->engine, p->dtype, p->boundary, p->k, inf.r1, inf.r2, ndim, p->fuse};
+    mix(key, sizeof key);
+    mix(p->w.data(), p->w.size() * sizeof(double));
+    p->klass = h;
     inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
     return SS_OK;
-}
-
-hipError_t sweep(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {
-    if (p->engine == SS_ENGINE_DIRECT) {
-        DirectArgs a = p->dargs;
-        a.in = in;
-        a.out = out;
-        return launch_direct(a, p->dtype == SS_F64, s);
-    }
-    MmaArgs a = p->margs;
-    a.in = static_cast<const float *>(in);
-    a.out = static_cast<float *>(out);
-    return p->mma(a, s);
 }
 
 template <class T>
@@ -460,6 +430,43 @@ ss_status copy_out(const std::vector<T> &v, void *buf, size_t *nbytes) {
 }
 
 }  // namespace
+
+namespace ss {
+// One sweep of the plan over n grids of its own shape class (same tables,
+// same boundary): one kernel launch.  dims_j = (nz, ny, nx) of grid j.
+hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
+                       const int64_t (*dims)[3], hipStream_t s) {
+    if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
+    if (p->engine == SS_ENGINE_DIRECT) {
+        DirectArgs a = p->dargs;
+        a.njobs = n;
+        for (int j = 0; j < n; ++j)
+            a.job[j] = DirectJob{in[j], out[j], (int)dims[j][0], (int)dims[j][1], (int)dims[j][2], 0};
+        return launch_direct(a, p->dtype == SS_F64, s);
+    }
+    MmaArgs a = p->margs;
+    a.njobs = n;
+    for (int j = 0; j < n; ++j)
+        a.job[j] = MmaJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],
+                          (int)dims[j][2], 0};
+    return p->mma(a, s);
+}
+
+hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {
+    void *o = out;
+    return sweep_grids(p, 1, &in, &o, &p->dims, s);
+}
+
+
+size_t plan_state_bytes(const ss_plan_ *p) { return state_bytes(p->dtype); }
+
+bool same_class(const ss_plan_ *a, const ss_plan_ *b) {
+    return a->klass == b->klass && a->engine == b->engine && a->dtype == b->dtype &&
+           a->boundary == b->boundary && a->k == b->k && a->ndim == b->ndim && a->fuse == b->fuse &&
+           a->info.r1 == b->info.r1 && a->info.r2 == b->info.r2 && a->w == b->w;
+}
+
+}  // namespace ss
 
 extern "C" {
 
@@ -506,7 +513,7 @@ ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void 
     }
     for (int64_t i = 0; i < total; ++i) {
         const ss_plan_ *q = i < fused ? p : p->rem;
-        if (sweep(q, src, dst, s) != hipSuccess) return SS_E_DEVICE;
+        if (ss::sweep_one(q, src, dst, s) != hipSuccess) return SS_E_DEVICE;
         std::swap(src, dst);
     }
     return SS_OK;
@@ -514,7 +521,7 @@ ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void 
 
 ss_status sparstencil_sweep(ss_plan_t p, const void *in, void *out, void *stream) {
     if (!p || !in || !out || in == out || p->host_only) return SS_E_INVALID;
-    return sweep(p, in, out, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK : SS_E_DEVICE;
+    return ss::sweep_one(p, in, out, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK : SS_E_DEVICE;
 }
 
 ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *nbytes) {

@@ -27,7 +27,9 @@ ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
 
 EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
            "sparstencil_sweep", "sparstencil_launch_count", "sparstencil_grid_bytes",
-           "sparstencil_status_string"]
+           "sparstencil_status_string", "sparstencil_server_create", "sparstencil_submit",
+           "sparstencil_poll", "sparstencil_job_release", "sparstencil_server_drain",
+           "sparstencil_server_clock", "sparstencil_server_destroy"]
 
 
 class SparStencilError(RuntimeError):
@@ -40,6 +42,15 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("boundary", ctypes.c_int32),
                 ("fuse_steps", ctypes.c_int32), ("r1", ctypes.c_int32), ("r2", ctypes.c_int32),
                 ("engine", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("state", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("steps_total", ctypes.c_int64), ("steps_done", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class PlanInfo(ctypes.Structure):
@@ -88,6 +99,21 @@ def lib():
         L.sparstencil_grid_bytes.argtypes = [vp]
         L.sparstencil_status_string.restype = ctypes.c_char_p
         L.sparstencil_status_string.argtypes = [i32]
+        u64 = ctypes.c_uint64
+        L.sparstencil_server_create.restype = i32
+        L.sparstencil_server_create.argtypes = [ctypes.POINTER(vp), vp, sz, i32, i32]
+        L.sparstencil_submit.restype = i32
+        L.sparstencil_submit.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(u64)]
+        L.sparstencil_poll.restype = i32
+        L.sparstencil_poll.argtypes = [vp, u64, ctypes.POINTER(JobInfo)]
+        L.sparstencil_job_release.restype = i32
+        L.sparstencil_job_release.argtypes = [vp, u64]
+        L.sparstencil_server_drain.restype = i32
+        L.sparstencil_server_drain.argtypes = [vp]
+        L.sparstencil_server_clock.restype = ctypes.c_double
+        L.sparstencil_server_clock.argtypes = [vp]
+        L.sparstencil_server_destroy.restype = i32
+        L.sparstencil_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -160,6 +186,45 @@ def sparstencil_status_string(status: int) -> str:
     return status_string(status)
 
 
+def sparstencil_server_create(arena, arena_bytes: int, max_jobs: int, num_streams: int = 4) -> int:
+    h = ctypes.c_void_p()
+    _check(lib().sparstencil_server_create(ctypes.byref(h), _ptr(arena), int(arena_bytes), int(max_jobs),
+                                           int(num_streams)), "sparstencil_server_create")
+    return int(h.value)
+
+
+def sparstencil_submit(server: int, plan: int, inp, out, steps: int) -> int:
+    jid = ctypes.c_uint64(0)
+    _check(lib().sparstencil_submit(server, plan, _ptr(inp), _ptr(out), int(steps), ctypes.byref(jid)),
+           "sparstencil_submit")
+    return int(jid.value)
+
+
+def sparstencil_poll(server: int, job_id: int):
+    """(status, info dict); status is SS_PENDING, SS_OK or the job's error."""
+    info = JobInfo()
+    st = lib().sparstencil_poll(server, int(job_id), ctypes.byref(info))
+    if st == SS_E_NOT_FOUND or st == SS_E_INVALID:
+        raise SparStencilError(st, "sparstencil_poll")
+    return st, info.as_dict()
+
+
+def sparstencil_job_release(server: int, job_id: int) -> None:
+    _check(lib().sparstencil_job_release(server, int(job_id)), "sparstencil_job_release")
+
+
+def sparstencil_server_drain(server: int) -> None:
+    _check(lib().sparstencil_server_drain(server), "sparstencil_server_drain")
+
+
+def sparstencil_server_clock(server: int) -> float:
+    return float(lib().sparstencil_server_clock(server))
+
+
+def sparstencil_server_destroy(server: int) -> None:
+    _check(lib().sparstencil_server_destroy(server), "sparstencil_server_destroy")
+
+
 # ----------------------------------------------------------------------------
 # convenience wrapper
 
@@ -225,3 +290,45 @@ class Plan:
     @property
     def grid_bytes(self) -> int:
         return sparstencil_grid_bytes(self.handle)
+
+
+class Server:
+    """Owns one server handle over a caller-provided device arena."""
+
+    def __init__(self, arena, arena_bytes, max_jobs=4096, num_streams=4):
+        self.handle = 0
+        self.arena = arena  # keeps the arena alive while the server runs
+        self.handle = sparstencil_server_create(arena, arena_bytes, max_jobs, num_streams)
+
+    def submit(self, plan, inp, out, steps) -> int:
+        h = plan.handle if isinstance(plan, Plan) else int(plan)
+        return sparstencil_submit(self.handle, h, inp, out, steps)
+
+    def poll(self, job_id):
+        return sparstencil_poll(self.handle, job_id)
+
+    def release(self, job_id):
+        sparstencil_job_release(self.handle, job_id)
+
+    def drain(self):
+        sparstencil_server_drain(self.handle)
+
+    def clock(self) -> float:
+        return sparstencil_server_clock(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", 0):
+            sparstencil_server_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,121 @@
+"""Serving loop through the C ABI.
+
+CPU: argument checks that run before any HIP call.  GPU: a mix of jobs of
+several plan classes, sizes and step counts through one server with an
+arena too small to admit them all at once; every result must be
+bit-identical to sparstencil_run of the same plan alone (each output point's
+arithmetic does not depend on which grids share a launch), and the job
+records must be consistent.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synthetic
+
+native = pytest.importorskip("paper_2506_22969_amd.native")
+
+
+def test_server_arguments_rejected_without_device():
+    lib = native.lib()
+    h = ctypes.c_void_p()
+    E = native.SS_E_INVALID
+    assert lib.sparstencil_server_create(None, ctypes.c_void_p(256), 1024, 4, 1) == E
+    assert lib.sparstencil_server_create(ctypes.byref(h), None, 1024, 4, 1) == E
+    assert lib.sparstencil_server_create(ctypes.byref(h), ctypes.c_void_p(256), 0, 4, 1) == E
+    assert lib.sparstencil_server_create(ctypes.byref(h), ctypes.c_void_p(256), 1024, 0, 1) == E
+    assert lib.sparstencil_server_create(ctypes.byref(h), ctypes.c_void_p(256), 1024, 4, 0) == E
+    assert lib.sparstencil_server_create(ctypes.byref(h), ctypes.c_void_p(256), 1024, 4, 17) == E
+    jid = ctypes.c_uint64()
+    assert lib.sparstencil_submit(None, None, None, None, 1, ctypes.byref(jid)) == E
+    assert lib.sparstencil_poll(None, 1, None) == E
+    assert lib.sparstencil_job_release(None, 1) == E
+    assert lib.sparstencil_server_drain(None) == E
+    assert lib.sparstencil_server_destroy(None) == native.SS_OK
+    assert lib.sparstencil_server_clock(None) == 0.0
+
+
+def test_job_info_layout():
+    # uint64 + 2 int32 + 2 int64 + 3 doubles
+    assert ctypes.sizeof(native.JobInfo) == 8 + 4 + 4 + 8 + 8 + 3 * 8
+
+
+@pytest.mark.gpu
+def test_server_mix_matches_run_alone():
+    torch = pytest.importorskip("torch")
+    dev = "cuda:0"
+    w9, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(512, 512))
+    w9b, _ = synthetic.random_coeffs("box", 1, 2, seed=5, grid_shape=(512, 512))
+    specs = [  # (coeffs, dims, dtype, engine, boundary, steps)
+        (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 7),
+        (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 3),
+        (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 12),
+        (w9b, (300, 520), "f32_split_f16", "smfmac", "zero", 5),
+        (w9, (129, 131), "f32_split_f16", "mfma", "periodic", 4),
+        (w9, (256, 1024), "f32_split_bf16", "smfmac", "periodic", 9),
+        (w9, (200, 300), "f32", "direct", "zero", 6),
+        (w9b, (96, 64, 80), None, "direct", "periodic", 3),
+    ]
+    plans, jobs = [], []
+    for i, (w, dims, dtype, engine, bc, steps) in enumerate(specs):
+        if len(dims) == 3:  # 3-D box of radius 1 built from the 2-D draw
+            w = synthetic.random_coeffs("box", 1, 3, seed=70, grid_shape=dims)[0]
+            dtype = "f32"
+        plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine)
+        plans.append(plan)
+        x0 = torch.from_numpy(synthetic.grid_f32(dims, seed=10 + i)).to(dev)
+        jobs.append((plan, x0, steps))
+
+    # reference: each job alone through sparstencil_run
+    refs = []
+    for plan, x0, steps in jobs:
+        a = x0.clone()
+        b = torch.empty_like(a)
+        plan.run(a, b, steps, torch.cuda.current_stream().cuda_stream)
+        refs.append(b)
+    torch.cuda.synchronize()
+
+    # arena for the largest job and half as much again: the rest must queue
+    largest = max(p.grid_bytes for p, _, _ in jobs)
+    arena_bytes = 3 * ((largest + 255) // 256 * 256)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
+    outs = [torch.full_like(x0, float("nan")) for _, x0, _ in jobs]
+    with native.Server(arena, arena_bytes, max_jobs=64, num_streams=3) as srv:
+        ids = [srv.submit(plan, x0, out, steps) for (plan, x0, steps), out in zip(jobs, outs)]
+        srv.drain()
+        infos = []
+        for jid, (plan, x0, steps) in zip(ids, jobs):
+            st, info = srv.poll(jid)
+            assert st == native.SS_OK, info
+            assert info["state"] == 2 and info["status"] == 0
+            assert info["steps_done"] == info["steps_total"] == steps
+            assert info["t_submit"] <= info["t_admit"] <= info["t_done"] <= srv.clock()
+            infos.append(info)
+            srv.release(jid)
+            with pytest.raises(native.SparStencilError):
+                srv.poll(jid)
+        # the arena cannot hold every job at once, so some were admitted late
+        assert max(i["t_admit"] for i in infos) > min(i["t_done"] for i in infos)
+    torch.cuda.synchronize()
+    for i, (out, ref) in enumerate(zip(outs, refs)):
+        assert torch.equal(out, ref), f"job {i} differs from the job run alone"
+    for p in plans:
+        p.close()
+
+
+@pytest.mark.gpu
+def test_server_rejects_job_larger_than_arena():
+    torch = pytest.importorskip("torch")
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
+    arena = torch.empty(4096, dtype=torch.uint8, device="cuda:0")
+    with native.Plan("box", 1, w, (64, 64), "f32_split_f16") as plan, \
+            native.Server(arena, 4096, max_jobs=2, num_streams=1) as srv:
+        x = torch.zeros(64, 64, device="cuda:0")
+        y = torch.empty_like(x)
+        with pytest.raises(native.SparStencilError) as e:
+            srv.submit(plan, x, y, 3)
+        assert e.value.status == native.SS_E_NOMEM
+        with pytest.raises(native.SparStencilError) as e:
+            srv.submit(plan, x, y, 0)
+        assert e.value.status == native.SS_E_INVALID
