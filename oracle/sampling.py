@@ -12,33 +12,42 @@ from . import direct
 
 
 def cone_sample(x0: np.ndarray, w: np.ndarray, steps: int, points, periodic: bool = False):
-    """Oracle values after `steps` sweeps at the given points of a 2-D grid,
-    each computed on its dependency cone only.
+    """Oracle values after `steps` sweeps at the given points of a 1-, 2- or
+    3-D grid (points are index tuples), each computed on its dependency cone
+    only.
 
-    A point after T sweeps depends on inputs within T*r of it.  Running the
-    oracle on that window (clipped to the grid for a zero halo) gives the exact
-    value at the window's centre: whatever the window's own edges get wrong
-    travels inward at r points per sweep and cannot reach the centre in T
-    sweeps.  Periodic grids take the window with wrapped indices.
+    A point after T sweeps depends on inputs within T*r of it along every
+    axis.  Running the oracle on that window (clipped to the grid for a zero
+    halo) gives the exact value at the window's centre: whatever the window's
+    own edges get wrong travels inward at r points per sweep and cannot reach
+    the centre in T sweeps.  Periodic grids take the window with wrapped
+    indices.
     """
     r = (w.shape[0] - 1) // 2
-    ny, nx = x0.shape
     reach = steps * r
     out = []
-    for (y, x) in points:
+    for pt in points:
         if periodic:
-            ys = np.arange(y - reach, y + reach + 1) % ny
-            xs = np.arange(x - reach, x + reach + 1) % nx
-            win = x0[np.ix_(ys, xs)].astype(np.float64)
+            idx = [np.arange(c - reach, c + reach + 1) % n for c, n in zip(pt, x0.shape)]
+            win = x0[np.ix_(*idx)].astype(np.float64)
             res = direct.run(win, w, steps, periodic=False)
-            out.append(res[reach, reach])
+            out.append(res[(reach,) * x0.ndim])
         else:
-            y0, y1 = max(0, y - reach), min(ny, y + reach + 1)
-            x0_, x1 = max(0, x - reach), min(nx, x + reach + 1)
-            win = x0[y0:y1, x0_:x1].astype(np.float64)
+            lo = [max(0, c - reach) for c in pt]
+            hi = [min(n, c + reach + 1) for c, n in zip(pt, x0.shape)]
+            win = x0[tuple(slice(a, b) for a, b in zip(lo, hi))].astype(np.float64)
             res = direct.run(win, w, steps, periodic=False)
-            out.append(res[y - y0, x - x0_])
+            out.append(res[tuple(c - a for c, a in zip(pt, lo))])
     return np.array(out)
+
+
+def sample_points3(nz: int, ny: int, nx: int, n: int, seed: int = 0):
+    """Corners of the box and seeded interior points."""
+    pts = [(z, y, x) for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)]
+    g = np.random.Generator(np.random.PCG64(seed))
+    while len(pts) < n:
+        pts.append((int(g.integers(nz)), int(g.integers(ny)), int(g.integers(nx))))
+    return pts
 
 
 def sample_points(ny: int, nx: int, n: int, seed: int = 0):

@@ -1,5 +1,5 @@
 // Direct stencil sweep on the vector ALUs: the same-box baseline for the
-// matrix-core engines.  Each thread produces RY consecutive outputs along y
+// matrix-core engines (FP32, FP64 or bfloat16 hi/lo-plane states).  Each thread produces RY consecutive outputs along y
 // of one column, reading each input row segment of its window once.
 #include <hip/hip_runtime.h>
 
@@ -12,8 +12,42 @@ __device__ inline int wrap_i(int i, int n) {
     return i < 0 ? i + n : i;
 }
 
-template <typename T, int RAD, int RY>
+// Element access of the three state kinds: FP32 and FP64 values as stored;
+// planes as hi + lo (exact in FP32), written back as hi = RNE(y),
+// lo = RNE(y - hi).
+template <int KIND>
+struct StateIo;
+template <>
+struct StateIo<kDirectF32> {
+    using T = float;
+    __device__ static float load(const void *p, size_t, size_t i) { return static_cast<const float *>(p)[i]; }
+    __device__ static void store(void *p, size_t, size_t i, float y) { static_cast<float *>(p)[i] = y; }
+};
+template <>
+struct StateIo<kDirectF64> {
+    using T = double;
+    __device__ static double load(const void *p, size_t, size_t i) { return static_cast<const double *>(p)[i]; }
+    __device__ static void store(void *p, size_t, size_t i, double y) { static_cast<double *>(p)[i] = y; }
+};
+template <>
+struct StateIo<kDirectPlanes> {
+    using T = float;
+    __device__ static float load(const void *p, size_t plane, size_t i) {
+        const __bf16 *b = static_cast<const __bf16 *>(p);
+        return (float)b[i] + (float)b[plane + i];
+    }
+    __device__ static void store(void *p, size_t plane, size_t i, float y) {
+        __bf16 *b = static_cast<__bf16 *>(p);
+        const __bf16 h = (__bf16)y;
+        b[i] = h;
+        b[plane + i] = (__bf16)(y - (float)h);
+    }
+};
+
+template <int KIND, int RAD, int RY>
 __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
+    using IO = StateIo<KIND>;
+    using T = typename IO::T;
     // block -> (job, z, row block, column block)
     const int b = blockIdx.x;
     int j = 0;
@@ -28,9 +62,8 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
     const int x = bx * 64 + (threadIdx.x & 63);
     const int y0 = (by * 4 + (threadIdx.x >> 6)) * RY;
     if (x >= g.nx || y0 >= g.ny) return;
-    const T *in = static_cast<const T *>(g.in);
+    const size_t plane = (size_t)g.nz * g.ny * g.nx;
     const T *w = static_cast<const T *>(a.w);
-    T *out = static_cast<T *>(g.out);
     const int kz = 2 * a.rz + 1, ky = 2 * a.ry + 1, kx = 2 * a.rx + 1;
     T acc[RY];
 #pragma unroll
@@ -43,15 +76,15 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
             int yy = y0 - a.ry + yi;
             if (a.periodic) yy = wrap_i(yy, g.ny);
             else if (yy < 0 || yy >= g.ny) continue;
-            const T *row = in + ((size_t)zz * g.ny + yy) * g.nx;
+            const size_t row = ((size_t)zz * g.ny + yy) * g.nx;
             T v[2 * RAD + 1];
 #pragma unroll
             for (int c = 0; c < 2 * RAD + 1; ++c) {
                 v[c] = T(0);
                 if (c < kx) {
                     int xx = x - a.rx + c;
-                    if (a.periodic) v[c] = row[wrap_i(xx, g.nx)];
-                    else if (xx >= 0 && xx < g.nx) v[c] = row[xx];
+                    if (a.periodic) v[c] = IO::load(g.in, plane, row + wrap_i(xx, g.nx));
+                    else if (xx >= 0 && xx < g.nx) v[c] = IO::load(g.in, plane, row + xx);
                 }
             }
 #pragma unroll
@@ -67,10 +100,10 @@ __global__ __launch_bounds__(256) void k_direct(DirectArgs a) {
     }
 #pragma unroll
     for (int jj = 0; jj < RY; ++jj)
-        if (y0 + jj < g.ny) out[((size_t)z * g.ny + y0 + jj) * g.nx + x] = acc[jj];
+        if (y0 + jj < g.ny) IO::store(g.out, plane, ((size_t)z * g.ny + y0 + jj) * g.nx + x, acc[jj]);
 }
 
-template <typename T, int RAD>
+template <int KIND, int RAD>
 static hipError_t launch_t(DirectArgs &a, hipStream_t s) {
     constexpr int RY = 4;
     int blocks = 0;
@@ -81,23 +114,28 @@ static hipError_t launch_t(DirectArgs &a, hipStream_t s) {
     }
     a.total_blocks = blocks;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_direct<T, RAD, RY>), dim3(blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_direct<KIND, RAD, RY>), dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
+template <int KIND>
 static hipError_t launch_r(DirectArgs &a, hipStream_t s) {
     const int r = a.rx;
-    if (r <= 1) return launch_t<T, 1>(a, s);
-    if (r <= 2) return launch_t<T, 2>(a, s);
-    if (r <= 3) return launch_t<T, 3>(a, s);
-    if (r <= 6) return launch_t<T, 6>(a, s);
+    if (r <= 1) return launch_t<KIND, 1>(a, s);
+    if (r <= 2) return launch_t<KIND, 2>(a, s);
+    if (r <= 3) return launch_t<KIND, 3>(a, s);
+    if (r <= 6) return launch_t<KIND, 6>(a, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_direct(DirectArgs &a, int is_f64, hipStream_t s) {
+hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s) {
     if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
-    return is_f64 ? launch_r<double>(a, s) : launch_r<float>(a, s);
+    switch (kind) {
+        case kDirectF32: return launch_r<kDirectF32>(a, s);
+        case kDirectF64: return launch_r<kDirectF64>(a, s);
+        case kDirectPlanes: return launch_r<kDirectPlanes>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace ss

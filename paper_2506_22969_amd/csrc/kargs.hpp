@@ -15,13 +15,15 @@ enum PartType { kPartF16 = 0, kPartBF16 = 1 };
 constexpr int kMaxJobs = 16;
 
 struct MmaJob {
-    const float *in;
-    float *out;
+    const void *in;
+    void *out;
     int ny, nx;
     int item0;
+    int nz, zc;              // 3-D: planes, and planes per work item
 };
 
-// 2-D MMA sweep on an FP32 state split into hi+lo parts in the kernel.
+// 2-D MMA sweep: FP32 state split into hi+lo parts in the kernel, or a state
+// of bfloat16 hi and lo planes.
 struct MmaArgs {
     int njobs;
     int total_items;         // work items over all jobs
@@ -32,8 +34,8 @@ struct MmaArgs {
     const uint4 *a_hi;       // [MB][KC][64] A fragments (8 x 16-bit each)
     const uint4 *a_lo;
     const uint32_t *a_idx;   // [MB][KC][64] sparse index words (sparse mode)
-    const int32_t *boff;     // [KC][4][VPK] gather offsets in floats
-    const float *zeros;      // 1 KiB of zeros (loads outside a zero-halo grid)
+    const int32_t *boff;     // [KC][4][VPK] gather offsets in state elements
+    const void *zeros;       // 1 KiB of zeros (loads outside a zero-halo grid)
 };
 
 struct DirectJob {
@@ -50,21 +52,34 @@ struct DirectArgs {
     DirectJob job[kMaxJobs];
     int rz, ry, rx;
     int periodic;
-    const void *w;           // coefficients, same type as the state
+    const void *w;           // coefficients (FP64 for an FP64 state, else FP32)
 };
 
 // Key of an instantiated 2-D MMA kernel.
 struct MmaKey {
-    int r1, r2, kc, rad, mode, part;
+    int r1, r2, kc, rad, mode, part, state;
 };
 
 // Returns nullptr when no kernel is instantiated for the key.  The launch
 // fills total_items and the jobs' item0 from their grid sizes.
 using MmaLaunch = hipError_t (*)(MmaArgs &, hipStream_t);
 MmaLaunch find_mma2d(const MmaKey &key);
-bool mma2d_geometry(const MmaKey &key, int *wgh, int *cpitch);
+// Rows of a work item and the slab's elements between source rows.
+bool mma2d_geometry(const MmaKey &key, int *wgh, int *row);
+// Instantiated keys with the given radius, mode, part and state (at most max).
+int mma2d_keys(int rad, int mode, int part, int state, MmaKey *out, int max);
+
+// State types of the direct engine: FP32, FP64 (coefficients of the same
+// type), bfloat16 hi and lo planes (FP32 coefficients and arithmetic).
+enum DirectKind { kDirectF32 = 0, kDirectF64 = 1, kDirectPlanes = 2 };
+
+// 3-D MMA kernels (FP32 state), same conventions; the launch also fills the
+// jobs' z-chunk depth zc.
+MmaLaunch find_mma3d(const MmaKey &key);
+bool mma3d_geometry(const MmaKey &key, int *wgh, int *row);
+int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max);
 
 // Fills total_blocks and the jobs' block0 from their grid sizes.
-hipError_t launch_direct(DirectArgs &a, int is_f64, hipStream_t s);
+hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s);
 
 }  // namespace ss

@@ -1,7 +1,8 @@
 // Geometry shared by the host runtime (table building, launch shapes) and the
 // 2-D MMA kernels.  A workgroup of 512 threads (8 waves of 64) owns a band 256
-// outputs wide; an N-block is the 16 tiles one MMA covers along N (128
-// columns wide), and each wave multiplies one N-block of every work item.
+// outputs wide and 32 rows tall (a work item).  A unit is the 16 tiles one MMA
+// covers along N (128 columns wide, NBH rows); the waves sit 2 across and 4
+// down the item and each multiplies U units stacked vertically.
 #pragma once
 
 namespace ss {
@@ -9,23 +10,80 @@ namespace ss {
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kBandX = 256;      // outputs per workgroup along x
-constexpr int kNbCols = 2;       // N-blocks side by side across a band
-constexpr int kSlabs = 4;        // LDS slabs in the load pipeline
+constexpr int kNbCols = 2;       // units side by side across a band
+constexpr int kItemRows = 32;    // rows of a work item
+constexpr int kLdsBytes = 160 * 1024;
 
-template <int R1, int R2, int RAD>
+// State layouts: FP32 values, or bfloat16 hi and lo planes ([hi | lo], each
+// a full grid of 16-bit values).
+enum State { kStateF32 = 0, kStatePlanes = 1 };
+
+template <int R1, int R2, int RAD, int STATE>
 struct MmaGeom {
     static constexpr int MB = R1 * R2 / 16;            // 16-row M-blocks of A'
-    static constexpr int NBX = 128 / R1;               // tiles of an N-block along x
+    static constexpr int NBX = 128 / R1;               // tiles of a unit along x
     static constexpr int NBY = 16 / NBX;               // ... along y
-    static constexpr int NBH = NBY * R2;               // rows of an N-block
-    static constexpr int WGH = kWaves / kNbCols * NBH;  // rows of a work item
+    static constexpr int NBH = NBY * R2;               // rows of a unit
+    static constexpr int U = kItemRows / (kWaves / kNbCols * NBH);  // units per wave
+    static constexpr int WGH = kWaves / kNbCols * U * NBH;          // rows of a work item
+    static_assert(WGH == kItemRows, "tile does not divide the work item");
     static constexpr int SROWS = WGH + 2 * RAD;        // slab rows
-    // FP32 slab rows: HL columns of left margin (>= RAD, a multiple of 4, so
-    // that the interior columns start 16-byte aligned), the band, RAD right
+    // FP32 slab rows (floats): HL columns of left margin (>= RAD, a multiple
+    // of 4 so that the interior starts 16-byte aligned), the band, RAD right
     // halo columns, padding to a multiple of 4 plus 4.
     static constexpr int HL = (RAD + 3) / 4 * 4;
-    static constexpr int CPITCH = (HL + kBandX + RAD + 3) / 4 * 4 + 4;  // floats per slab row
-    static constexpr int SLAB_F = SROWS * CPITCH;                       // floats per slab
+    static constexpr int CPITCH = (HL + kBandX + RAD + 3) / 4 * 4 + 4;
+    // Planes slab (bfloat16 elements): a hi part of SROWS rows of PB
+    // elements, then a lo part of the same shape (LO elements further on).
+    // Rows have an 8-element left margin and up to 8 right halo columns;
+    // halo columns move in pairs (HD dwords per side and plane).  PB/2 dwords
+    // is 4 mod 8, so that vertically adjacent tiles start in different LDS
+    // banks; PB is a multiple of 8 so that every row starts 16-byte aligned.
+    static constexpr int HLB = 8;
+    static constexpr int PB = 280;
+    static constexpr int LO = SROWS * PB;
+    static constexpr int HD = (RAD + 1) / 2;
+    static_assert(STATE == kStateF32 || 2 * HD <= HLB, "halo wider than the margin");
+    static_assert(PB >= HLB + kBandX + 2 * HD && PB % 8 == 0 && (PB / 2) % 8 == 4, "plane row pitch");
+    // with an even radius every B register's two values share one dword
+    // (tile origins and pair columns are even)
+    static constexpr bool PAIR_DWORD = STATE == kStatePlanes && RAD % 2 == 0;
+    // per slab: elements between consecutive source rows, left margin, bytes
+    static constexpr int ROW = STATE == kStateF32 ? CPITCH : PB;
+    static constexpr int MARGIN = STATE == kStateF32 ? HL : HLB;
+    static constexpr int SLAB_BYTES = STATE == kStateF32 ? SROWS * CPITCH * 4 : 2 * SROWS * PB * 2;
+    // halo dwords of one slab, and the staging strip they land in (whole
+    // 512-lane transfers)
+    static constexpr int HALO_ROW = STATE == kStateF32 ? 2 * RAD : 4 * HD;
+    static constexpr int NHALO = SROWS * HALO_ROW;
+    static constexpr int HOPS = (NHALO + kThreads - 1) / kThreads;
+    static constexpr int HSTRIP = HOPS * kThreads;
+    // pipeline depth: four slabs when they fit, else three
+    static constexpr int NSLAB = 4 * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes ? 4 : 3;
+    static_assert(NSLAB * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes, "slabs exceed LDS");
+};
+
+// 3-D kernel: a work item is a column of the grid (a 256-column band of
+// WGH rows) over a range of z planes; the workgroup marches through z with a
+// ring of NP plane slabs in LDS, each output plane using the 2*RAD+1 input
+// planes around it.  Each wave multiplies one unit (16 tiles) per plane.
+template <int R1, int R2, int RAD>
+struct Mma3Geom {
+    static constexpr int MB = R1 * R2 / 16;
+    static constexpr int NBX = 128 / R1;
+    static constexpr int NBY = 16 / NBX;
+    static constexpr int NBH = NBY * R2;
+    static constexpr int WGH = kWaves / kNbCols * NBH;  // rows of a work item
+    static constexpr int SROWS = WGH + 2 * RAD;
+    static constexpr int HL = (RAD + 3) / 4 * 4;
+    static constexpr int CPITCH = (HL + kBandX + RAD + 3) / 4 * 4 + 4;
+    static constexpr int PLANE_BYTES = SROWS * CPITCH * 4;
+    static constexpr int NHALO = SROWS * 2 * RAD;       // halo dwords per plane (moved by wave 0)
+    static constexpr int HOPS = (NHALO + 63) / 64;
+    static constexpr int HSTRIP = HOPS * 64;
+    static constexpr int SLOT = PLANE_BYTES + 4 * HSTRIP;
+    static constexpr int NP = kLdsBytes / SLOT < 8 ? kLdsBytes / SLOT : 8;  // ring slots
+    static_assert(NP >= 2 * RAD + 2, "ring too small for the stencil depth");
 };
 
 }  // namespace ss

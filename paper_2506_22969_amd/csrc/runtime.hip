@@ -11,6 +11,7 @@
 
 #include "../../include/sparstencil.h"
 #include "kargs.hpp"
+#include "kgeom.hpp"
 #include "plan.hpp"
 #include "planner.hpp"
 
@@ -47,11 +48,14 @@ bool valid_star(const std::vector<double> &w, int ndim, int r) {
     return true;
 }
 
-// Fill the 2-D MMA kernel tables.  Sparse: compressed A'' in the SMFMAC
-// operand layout with its index words; dense: A' in natural column order.
-// Gather offsets are in floats from the tile's patch origin in the slab.
-ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, int kc_count,
-                           int cpitch, std::vector<uint8_t> *blob, size_t *off_hi,
+// Fill the MMA kernel tables for the kernel's K order `kperm` (A' column per
+// K slot, kZeta for zero columns).  Sparse: compressed A'' in the SMFMAC
+// operand layout with its index words; dense: A' columns in kperm order.
+// Gather offsets are in state elements from the tile's patch origin within
+// one input plane of the slab, whose rows are `pitch` elements apart (the
+// 3-D kernel picks the plane per K chunk).
+ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<int> &kperm, int mode, int part,
+                           int kc_count, int pitch, std::vector<uint8_t> *blob, size_t *off_hi,
                            size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
     const int MB = gm.m_prime() / 16;
     const std::vector<double> amat = morph_matrix(gm, p->w);
@@ -65,26 +69,28 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, 
         return to_bf16_bits(c - bf16_value(*h), l);
     };
     const int VPK = mode == kSparse ? 8 : 4;
+    if ((int)kperm.size() != kc_count * (mode == kSparse ? 64 : 32)) return SS_E_UNSUPPORTED;
     std::vector<uint16_t> ahi((size_t)MB * kc_count * 64 * 8), alo(ahi.size());
     std::vector<uint32_t> aidx((size_t)MB * kc_count * 64, 0);
     std::vector<int32_t> boff((size_t)kc_count * 4 * VPK, 0);
     if (mode == kSparse) {
-        const int groups = (int)p->perm.size() / 4;
+        Compressed cm;
+        if (!compress(gm, amat, kperm, &cm)) return SS_E_UNSUPPORTED;
+        const int groups = (int)kperm.size() / 4;
         for (int mb = 0; mb < MB; ++mb)
             for (int kc = 0; kc < kc_count; ++kc)
                 for (int l = 0; l < 64; ++l) {
-                    const int row = mb * 16 + (l & 15), qa = l >> 4;
+                    const int r = mb * 16 + (l & 15), qa = l >> 4;
                     uint32_t word = 0;
                     for (int ea = 0; ea < 8; ++ea) {
                         const int gl = ea >> 1, s = ea & 1;
                         const int qb = 2 * (qa & 1) + (gl >> 1);
                         const int m = 2 * (qa >> 1) + (gl & 1);
-                        const int j = kc * 16 + 4 * qb + m;     // canonical 4-group
-                        const size_t vi = ((size_t)row * groups + j) * 2 + s;
+                        const int j = kc * 16 + 4 * qb + m;     // 4-group of the K order
+                        const size_t vi = ((size_t)r * groups + j) * 2 + s;
                         const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + ea;
-                        ahi[t] = p->hi[vi];
-                        alo[t] = p->lo[vi];
-                        word |= (uint32_t)p->meta[vi] << (2 * ea);
+                        if (!split(cm.values[vi], &ahi[t], &alo[t])) return SS_E_UNSUPPORTED;
+                        word |= (uint32_t)cm.meta[vi] << (2 * ea);
                     }
                     aidx[((size_t)mb * kc_count + kc) * 64 + l] = word;
                 }
@@ -93,26 +99,24 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, int mode, int part, 
             for (int kc = 0; kc < kc_count; ++kc)
                 for (int l = 0; l < 64; ++l)
                     for (int e = 0; e < 8; ++e) {
-                        const int row = mb * 16 + (l & 15);
-                        const int col = kc * 32 + 8 * (l >> 4) + e;
-                        const double c = col < kp ? amat[(size_t)row * kp + col] : 0.0;
-                        uint16_t h, lw;
-                        if (!split(c, &h, &lw)) return SS_E_UNSUPPORTED;
+                        const int r = mb * 16 + (l & 15);
+                        const int col = kperm[kc * 32 + 8 * (l >> 4) + e];
+                        const double c = col != kZeta && col < kp ? amat[(size_t)r * kp + col] : 0.0;
                         const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + e;
-                        ahi[t] = h;
-                        alo[t] = lw;
+                        if (!split(c, &ahi[t], &alo[t])) return SS_E_UNSUPPORTED;
                     }
     }
     // gather offsets: K slot pair (kk, kk+1) of B register v of lane group qb
+    const int plane = gm.m_b * gm.g;
     for (int kc = 0; kc < kc_count; ++kc)
         for (int qb = 0; qb < 4; ++qb)
             for (int v = 0; v < VPK; ++v) {
                 const int kk = mode == kSparse ? kc * 64 + 16 * qb + 2 * v : kc * 32 + 8 * qb + 2 * v;
-                int col = mode == kSparse ? p->perm[kk] : (kk < kp ? kk : kZeta);
+                const int col = kperm[kk];
                 int32_t o = 0;
                 if (col != kZeta) {
-                    const int pr = (col % (gm.m_b * gm.g)) / gm.g, pc = col % gm.g;
-                    o = pr * cpitch + pc;
+                    const int pr = (col % plane) / gm.g, pc = col % gm.g;
+                    o = pr * pitch + pc;
                 }
                 boff[((size_t)kc * 4 + qb) * VPK + v] = o;
             }
@@ -180,57 +184,57 @@ ss_status upload(ss_plan_ *p, const std::vector<uint8_t> &blob) {
     return SS_OK;
 }
 
-struct Candidate {
-    int r1, r2;
-};
-
-const Candidate kCandidates2d[] = {{8, 8}, {16, 4}};
+// State layout of a dtype on the MMA path.
+int mma_state(int dtype) { return dtype == SS_SPLIT_BF16 ? kStatePlanes : kStateF32; }
 
 ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
+    const int state = mma_state(p->dtype);
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
-    const int kfrag = mode == kSparse ? 64 : 32;
+    // the planes kernels move rows in 8-value (16-byte) pieces
+    if (state == kStatePlanes && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
     ModelParams mp{};
     mp.ndim = p->ndim;
     mp.k = p->k;
     for (int d = 0; d < 3; ++d) mp.dims[d] = d < p->ndim ? p->dims[3 - p->ndim + d] : 1;
-    mp.elem_bytes = 4;
+    mp.elem_bytes = state == kStatePlanes ? 2 : 4;
+    mp.planes_state = state == kStatePlanes ? 2 : 1;
     mp.coef_bytes = 2;
     mp.passes = 3;
-    mp.planes_state = 1;
     mp.kfrag = 64;
-    // candidates this build has kernels for
-    std::vector<Candidate> cands;
-    for (const Candidate &c : kCandidates2d) {
+    // tiles this build has kernels for
+    MmaKey keys[32];
+    const int nkeys = mma2d_keys(p->rad, mode, part, state, keys, 32);
+    std::vector<MmaKey> cands;
+    for (int i = 0; i < nkeys; ++i) {
+        const MmaKey &c = keys[i];
         if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
         const Geometry gm = make_geometry(2, p->k, c.r1, c.r2);
-        int kc;
         if (mode == kSparse) {
             const std::vector<int> perm = group_pairs(matrix_pairs(gm), 64);
-            if (!pair_aligned(gm, perm)) continue;
-            kc = (int)perm.size() / 64;
+            if (!pair_aligned(gm, perm) || (int)perm.size() != 64 * c.kc) continue;
         } else {
-            if (gm.g % 2) continue;
-            kc = (gm.k_prime() + 31) / 32;
+            if (gm.g % 2 || (gm.k_prime() + 31) / 32 != c.kc) continue;
         }
-        if (!find_mma2d(MmaKey{c.r1, c.r2, kc, p->rad, mode, part})) continue;
         cands.push_back(c);
     }
     if (cands.empty()) return SS_E_UNSUPPORTED;
     ModelRow best{};
+    MmaKey key{};
     bool have = false;
     p->model.clear();
-    for (const Candidate &c : cands) {
+    for (const MmaKey &c : cands) {
         const ModelRow r = model_time(mp, c.r1, c.r2);
         const double row[7] = {(double)r.r1, (double)r.r2, r.t, r.t_compute, r.t_global, r.t_shared,
                                (double)r.k_pad};
         p->model.insert(p->model.end(), row, row + 7);
         if (!have || model_better(r, best)) {
             best = r;
+            key = c;
             have = true;
         }
     }
-    const Geometry gm = make_geometry(2, p->k, best.r1, best.r2);
+    const Geometry gm = make_geometry(2, p->k, key.r1, key.r2);
     ss_status st = build_canonical(p, gm, part, 64);
     if (st != SS_OK) return st;
     if (mode == kDense) {
@@ -239,14 +243,18 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
         const int kd = (gm.k_prime() + 31) / 32 * 32;
         for (int c = 0; c < kd; ++c) p->perm.push_back(c < gm.k_prime() ? c : kZeta);
     }
-    const int kc = mode == kSparse ? (int)p->perm.size() / 64 : (int)p->perm.size() / 32;
-    const MmaKey key{best.r1, best.r2, kc, p->rad, mode, part};
-    int wgh, cpitch;
-    if (!mma2d_geometry(key, &wgh, &cpitch)) return SS_E_UNSUPPORTED;
+    int wgh, row;
+    if (!mma2d_geometry(key, &wgh, &row)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, mode, part, kc, cpitch, &blob, &o_hi, &o_lo, &o_idx, &o_boff, &o_zero);
+    st = build_mma_tables(p, gm, p->perm, mode, part, key.kc, row, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+                          &o_zero);
     if (st != SS_OK) return st;
+    // the planes kernels of an even radius read each B register as one
+    // dword: every gather offset must be even
+    if (state == kStatePlanes && p->rad % 2 == 0)
+        for (int32_t o : p->kernel_lut)
+            if (o % 2) return SS_E_UNSUPPORTED;
     st = upload(p, blob);
     if (st != SS_OK) return st;
     char *d = static_cast<char *>(p->dev);
@@ -257,7 +265,103 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
     p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
     p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
-    p->margs.zeros = reinterpret_cast<const float *>(d + o_zero);
+    p->margs.zeros = d + o_zero;
+    p->engine = engine;
+    p->info.r1 = gm.r1;
+    p->info.r2 = gm.r2;
+    p->info.m_b = gm.m_b;
+    p->info.g = gm.g;
+    p->info.planes = gm.planes;
+    p->info.m_prime = gm.m_prime();
+    p->info.k_prime = gm.k_prime();
+    p->info.k_pad = (int)p->perm.size();
+    p->info.passes = 3;
+    p->info.sigma = part == kPartF16 ? 2048.0 : 1.0;
+    return SS_OK;
+}
+
+// The FP32 gather reads each B register's two values from adjacent columns
+// of one patch row (two dword reads, any alignment).
+bool pairs_adjacent(const Geometry &gm, const std::vector<int> &perm) {
+    for (size_t kk = 0; kk + 1 < perm.size(); kk += 2) {
+        const int a = perm[kk], b = perm[kk + 1];
+        if (a == kZeta && b == kZeta) continue;
+        if (a == kZeta || b == kZeta || b != a + 1 || a % gm.g + 1 >= gm.g) return false;
+    }
+    return true;
+}
+
+// 3-D MMA engines (FP32 state).  The kernel's K order keeps every input
+// plane in whole chunks: each plane's own pair list (the 2-D matching of its
+// block staircase) grouped and padded to 64 columns (sparse), or its columns
+// in natural order padded to a multiple of 32 (dense).  The canonical tables
+// (queries) are those of the plain 3-D reading: plane lists concatenated,
+// then grouped and padded once.
+ss_status plan_mma3d(ss_plan_ *p, int engine) {
+    const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
+    const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    MmaKey keys[16];
+    const int nkeys = mma3d_keys(p->rad, mode, part, keys, 16);
+    const MmaKey *key = nullptr;
+    std::vector<int> kperm;
+    for (int i = 0; i < nkeys && !key; ++i) {
+        const MmaKey &c = keys[i];
+        if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
+        const Geometry g2 = make_geometry(2, p->k, c.r1, c.r2);
+        const int plane = g2.m_b * g2.g, cpp = c.kc / p->k;
+        std::vector<int> one;
+        if (mode == kSparse) {
+            one = group_pairs(matrix_pairs(g2), 64);
+            if (!pairs_adjacent(g2, one) || (int)one.size() != 64 * cpp) continue;
+        } else {
+            if (g2.g % 2 || cpp * 32 < plane || (cpp - 1) * 32 >= plane) continue;
+            for (int x = 0; x < cpp * 32; ++x) one.push_back(x < plane ? x : kZeta);
+            if ((int)one.size() != 32 * cpp) continue;
+        }
+        kperm.clear();
+        for (int pz = 0; pz < p->k; ++pz)
+            for (int x : one) kperm.push_back(x == kZeta ? kZeta : x + pz * plane);
+        key = &keys[i];
+    }
+    if (!key) return SS_E_UNSUPPORTED;
+    const Geometry gm = make_geometry(3, p->k, key->r1, key->r2);
+    ss_status st = build_canonical(p, gm, part, 64);
+    if (st != SS_OK) return st;
+    if (mode == kDense) {
+        p->perm.clear();
+        const int kd = (gm.k_prime() + 31) / 32 * 32;
+        for (int c = 0; c < kd; ++c) p->perm.push_back(c < gm.k_prime() ? c : kZeta);
+    }
+    // model rows of the one candidate (Eqs. 6-10 for the record)
+    ModelParams mp{};
+    mp.ndim = 3;
+    mp.k = p->k;
+    for (int d = 0; d < 3; ++d) mp.dims[d] = p->dims[d];
+    mp.elem_bytes = 4;
+    mp.planes_state = 1;
+    mp.coef_bytes = 2;
+    mp.passes = 3;
+    mp.kfrag = 64;
+    const ModelRow r = model_time(mp, key->r1, key->r2);
+    p->model.assign({(double)r.r1, (double)r.r2, r.t, r.t_compute, r.t_global, r.t_shared, (double)r.k_pad});
+    int wgh, pitch;
+    if (!mma3d_geometry(*key, &wgh, &pitch)) return SS_E_UNSUPPORTED;
+    std::vector<uint8_t> blob;
+    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+                          &o_zero);
+    if (st != SS_OK) return st;
+    st = upload(p, blob);
+    if (st != SS_OK) return st;
+    char *d = static_cast<char *>(p->dev);
+    p->mma = find_mma3d(*key);
+    p->margs.periodic = p->boundary == SS_BC_PERIODIC;
+    p->margs.inv_sigma = part == kPartF16 ? 1.0f / 2048.0f : 1.0f;
+    p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
+    p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
+    p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
+    p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
+    p->margs.zeros = d + o_zero;
     p->engine = engine;
     p->info.r1 = gm.r1;
     p->info.r2 = gm.r2;
@@ -363,13 +467,19 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     p->info.r2 = o.r2;
 
     ss_status st = SS_E_UNSUPPORTED;
-    const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16;
+    const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16 || dtype == SS_SPLIT_BF16;
     int engine = o.engine;
+    const bool split3 = split && dtype != SS_SPLIT_BF16;  // 3-D kernels take an FP32 state
     if (split && ndim == 2 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
         st = plan_mma2d(p, SS_ENGINE_SMFMAC);
         if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma2d(p, SS_ENGINE_MFMA);
     } else if (split && ndim == 2 && engine == SS_ENGINE_MFMA) {
         st = plan_mma2d(p, SS_ENGINE_MFMA);
+    } else if (split3 && ndim == 3 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
+        st = plan_mma3d(p, SS_ENGINE_SMFMAC);
+        if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma3d(p, SS_ENGINE_MFMA);
+    } else if (split3 && ndim == 3 && engine == SS_ENGINE_MFMA) {
+        st = plan_mma3d(p, SS_ENGINE_MFMA);
     }
     if (st != SS_OK && (engine == SS_ENGINE_DIRECT || engine == SS_ENGINE_AUTO) &&
         (dtype == SS_F32 || dtype == SS_F64 || split) && o.r1 == 0)
@@ -442,13 +552,13 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
         a.njobs = n;
         for (int j = 0; j < n; ++j)
             a.job[j] = DirectJob{in[j], out[j], (int)dims[j][0], (int)dims[j][1], (int)dims[j][2], 0};
-        return launch_direct(a, p->dtype == SS_F64, s);
+        const int kind = p->dtype == SS_F64 ? kDirectF64 : p->dtype == SS_SPLIT_BF16 ? kDirectPlanes : kDirectF32;
+        return launch_direct(a, kind, s);
     }
     MmaArgs a = p->margs;
     a.njobs = n;
     for (int j = 0; j < n; ++j)
-        a.job[j] = MmaJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],
-                          (int)dims[j][2], 0};
+        a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
     return p->mma(a, s);
 }
 

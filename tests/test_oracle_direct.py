@@ -142,3 +142,21 @@ def test_star_is_box_with_zeros():
     x = g.random((9, 8))
     L = bruteforce.operator_matrix((9, 8), 2, w, False)
     assert np.max(np.abs(direct.run(x, w, 1).reshape(-1) - L @ x.reshape(-1))) < 1e-14
+
+
+@pytest.mark.parametrize("shape,periodic", [((37, 41), False), ((37, 41), True),
+                                            ((11, 13, 17), False), ((11, 13, 17), True)])
+def test_cone_sample_equals_full_run(shape, periodic):
+    # dependency-cone sampling against stepping the whole grid
+    from oracle.sampling import cone_sample, sample_points, sample_points3
+    ndim = len(shape)
+    g = np.random.Generator(np.random.PCG64(3))
+    w = g.uniform(-1, 1, (3,) * ndim)
+    w /= np.abs(w).sum()
+    x = g.random(shape)
+    steps = 4
+    full = direct.run(x, w, steps, periodic=periodic)
+    pts = sample_points(*shape, 12, seed=4) if ndim == 2 else sample_points3(*shape, 12, seed=4)
+    got = cone_sample(x, w, steps, pts, periodic=periodic)
+    want = np.array([full[p] for p in pts])
+    assert np.allclose(got, want, rtol=0, atol=1e-14)

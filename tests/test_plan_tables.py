@@ -20,6 +20,8 @@ CASES = [
     ("box", 1, 2, (10240, 10240), 16, 4),
     ("star", 1, 2, (4096, 4096), 8, 8),
     ("box", 1, 2, (300, 257), 0, 0),
+    ("box", 1, 3, (512, 512, 512), 8, 4),
+    ("star", 1, 3, (64, 96, 128), 0, 0),
 ]
 
 
@@ -93,3 +95,48 @@ def test_invalid_arguments():
     big = w * 1e6
     with pytest.raises(native.SparStencilError):
         native.Plan("box", 1, big, (64, 64), "f32_split_f16", engine="smfmac", host_only=True)
+
+
+@pytest.mark.parametrize("shape,seed", [("star", 45), ("box", 277)])
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_radius3_planes_tables_and_model(shape, seed, fuse):
+    # Star-2D13P / Box-2D49P on bfloat16 hi+lo planes, unfused (k = 7) and
+    # with two fused sweeps (k = 13): the kernel's tables against the oracle's
+    # re-derivation from the (composed) coefficients, and the tile the model
+    # picks among the instantiated ones.
+    dims = (8192, 8192)
+    w, _ = synthetic.random_coeffs(shape, 3, 2, seed=seed, grid_shape=dims)
+    with native.Plan(shape, 3, w, dims, "split_bf16", boundary="periodic", fuse_steps=fuse,
+                     engine="smfmac", host_only=True) as p:
+        info = p.info
+        wc = p.table(native.Q_COEFFS)
+        rows = p.table(native.Q_MODEL).reshape(-1, 7)
+        wf = T.compose(w, fuse) if fuse > 1 else w
+        k = 7 if fuse == 1 else 13
+        assert info["k"] == k
+        assert np.array_equal(wc, wf.reshape(-1))
+        a, s, d = T.morph(T.bounding_box("box", (k - 1) // 2, 2, wf), info["r1"], info["r2"])
+        pairs, zeros = T.plane_pairs(d)
+        perm = T.group(pairs, 64)
+        assert info["k_pad"] == len(perm) and info["zeros"] == zeros
+        assert np.array_equal(p.table(native.Q_PERM), np.array(perm, dtype=np.int32))
+        vals, meta = T.compress(a, s, perm)
+        assert np.array_equal(p.table(native.Q_VALUES), vals.reshape(-1))
+        assert np.array_equal(p.table(native.Q_META), meta.reshape(-1).astype(np.uint8))
+        hi, lo = T.split_hilo(vals, "bf16")
+        assert np.array_equal(p.table(native.Q_HI), hi.reshape(-1))
+        assert np.array_equal(p.table(native.Q_LO), lo.reshape(-1))
+    cands = [(int(r[0]), int(r[1])) for r in rows]
+    best, table = T.explore(k, 2, dims, cands, elem_bytes=2, coef_bytes=2, passes=3, planes_state=2)
+    for r in rows:
+        t = table[(int(r[0]), int(r[1]))][0]
+        assert r[2] == pytest.approx(t, rel=1e-12)
+    assert (info["r1"], info["r2"]) == best
+
+
+def test_planes_rows_must_be_a_multiple_of_8_for_mma():
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w, (64, 60), "split_bf16", engine="smfmac", host_only=True)
+    with native.Plan("box", 1, w, (64, 60), "split_bf16", host_only=True) as p:
+        assert p.info["engine_name"] == "direct"
