@@ -43,6 +43,8 @@ def parse():
                     help="jobs of the serving-mix leg (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="Poisson arrival rate as a fraction of the measured batch capacity")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
     return ap.parse_args()
 
 
@@ -132,6 +134,120 @@ def cpu_baseline(x0: np.ndarray, w: np.ndarray, gpu_out: np.ndarray, budget_s: f
             "kind": "oracle",
             "sample": f"{n} full-grid FP64 sweeps of the 10240^2 Box-2D9P grid ({dt:.1f} s); "
                       f"error check on 16 sampled outputs of the 100-sweep run via dependency cones"}, err
+
+
+def timed_run(torch, plan, x_dev, steps, stream, reps=1):
+    """Milliseconds of plan.run over `steps` sweeps (HIP events, median of
+    reps after one warm-up) and the output of the last run."""
+    a = torch.empty_like(x_dev)
+    b = torch.empty_like(x_dev)
+    a.copy_(x_dev)
+    plan.run(a, b, steps, stream.cuda_stream)
+    ms = []
+    for _ in range(reps):
+        a.copy_(x_dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.run(a, b, steps, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return float(np.median(ms)), b
+
+
+def workloads_leg(native, torch, stream):
+    """The other workloads of the study on every engine that runs them:
+    Heat-2D 256^2 FP64 (10 sweeps, zero halo), Star-2D13P / Box-2D49P on
+    8192^2 bfloat16 hi+lo planes (50 sweeps, 2-step fusion, periodic) and
+    Heat-3D / Box-3D27P on 512^3 FP32 (20 sweeps, zero halo).  Returns the
+    timings and, per result, the inputs and GPU values at sampled points for
+    the oracle check."""
+    import synthetic
+
+    out, checks = {}, []
+
+    def record(name, shape, radius, w, dims, dtype, steps, engines, x_host, make_dev, periodic,
+               fuse=1, reps=3, pts=None, pick=None):
+        x_dev = make_dev(x_host)
+        entry = {}
+        for eng in engines:
+            with native.Plan(shape, radius, w, dims, dtype, boundary="periodic" if periodic else "zero",
+                             fuse_steps=fuse, engine=eng) as p:
+                info = p.info
+                ms, y = timed_run(torch, p, x_dev, steps, stream, reps)
+                pts_vals = None
+                if pts is not None:
+                    pts_vals = [pick(y, pt) for pt in pts]
+            points = int(np.prod(dims))
+            entry[eng] = {"gstencil_s": round(steps * points / ms / 1e6, 2), "ms_per_run": round(ms, 3),
+                          "tile": [info["r1"], info["r2"]], "k_pad": info["k_pad"]}
+            if pts is not None:
+                checks.append((name, eng, shape, radius, w, x_host, steps, periodic, pts, pts_vals, dtype))
+        out[name] = entry
+        del x_dev
+        torch.cuda.empty_cache()
+
+    # Heat-2D 256^2 FP64: the whole grid is small enough for a full oracle run
+    w = synthetic.heat2d_coeffs()
+    x = synthetic.grid_f64((256, 256), seed=0)
+    record("heat2d_256_f64_T10", "star", 1, w, (256, 256), "f64", 10, ["direct", "mfma"], x,
+           lambda h: torch.from_numpy(h).to("cuda:0"), False, reps=21, pts=[None],
+           pick=lambda y, pt: y.cpu().numpy())
+    # radius-3 stencils on bfloat16 planes, two fused sweeps per launch
+    bits = synthetic.grid_bf16_planes((8192, 8192), seed=0)
+    for name, shape, seed in [("star2d13p_8192_planes_S2_T50", "star", 45), ("box2d49p_8192_planes_S2_T50", "box", 277)]:
+        w = synthetic.random_coeffs(shape, 3, 2, seed=seed, grid_shape=(8192, 8192))[0]
+        pts = [(0, 0), (4095, 17), (8191, 8191), (1234, 6543)]
+        record(name, shape, 3, w, (8192, 8192), "split_bf16", 50, ["smfmac", "mfma", "direct"], bits,
+               lambda h: torch.from_numpy(h.view(np.int16)).to("cuda:0"), True, fuse=2, pts=pts,
+               pick=lambda y, pt: y[:, pt[0], pt[1]].cpu().numpy().view(np.uint16).copy())
+    del bits
+    # 3-D 512^3 FP32
+    x3 = synthetic.grid_f32((512, 512, 512), seed=0)
+    for name, shape, seed in [("heat3d7p_512_T20", "star", 29), ("box3d27p_512_T20", "box", 70)]:
+        w = synthetic.random_coeffs(shape, 1, 3, seed=seed)[0]
+        pts = [(0, 0, 0), (255, 100, 511), (511, 511, 3), (17, 300, 200)]
+        record(name, shape, 1, w, (512, 512, 512), "f32_split_f16", 20, ["smfmac", "mfma", "direct"], x3,
+               lambda h: torch.from_numpy(h).to("cuda:0"), False, pts=pts,
+               pick=lambda y, pt: float(y[pt].item()))
+    return out, checks
+
+
+def check_workloads(checks):
+    """Oracle side of workloads_leg: normwise error of each engine's result
+    at its sampled points (the whole grid for Heat-2D)."""
+    from oracle import direct as oracle_direct
+    from oracle.sampling import cone_sample
+
+    errs = {}
+    cache = {}
+    for name, eng, shape, radius, w, x_host, steps, periodic, pts, vals, dtype in checks:
+        if dtype == "f64":
+            key = (name,)
+            if key not in cache:
+                cache[key] = oracle_direct.run(x_host, w, steps, periodic=periodic)
+            ref = cache[key]
+            got = vals[0]
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        else:
+            key = (name, "cones")
+            if key not in cache:
+                if dtype == "split_bf16":
+                    f = (x_host.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+                    x0 = f[0] + f[1]
+                else:
+                    x0 = x_host
+                cache[key] = cone_sample(x0, w, steps, pts, periodic=periodic)
+            ref = cache[key]
+            if dtype == "split_bf16":
+                got = np.array([float((v.astype(np.uint32) << 16).view(np.float32).astype(np.float64).sum())
+                                for v in vals])
+            else:
+                got = np.array(vals, dtype=np.float64)
+            err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        errs.setdefault(name, {})[eng] = err
+    return errs
 
 
 SERVE_DTYPES = {"f32": "f32_split_f16", "split_bf16": "f32_split_bf16"}
@@ -289,14 +405,22 @@ def main():
         "engines": results,
         "roofline": roof,
     }
+    del x0_dev
+    torch.cuda.empty_cache()
+    checks = []
+    if not args.no_workloads:
+        line["workloads"], checks = workloads_leg(native, torch, stream)
     if args.serve_jobs > 0:
-        del x0_dev
-        torch.cuda.empty_cache()
         line["serving"] = serving_leg(native, torch, args.serve_jobs, args.serve_load)
     if not args.no_cpu:
         cb, err = cpu_baseline(x0, w, gpu_out, args.cpu_seconds)
         line["cpu_baseline"] = cb
         line["error_vs_oracle"] = {"normwise_rel_sampled": err, "points": 16}
+        if checks:
+            errs = check_workloads(checks)
+            for name, per in errs.items():
+                for eng, e in per.items():
+                    line["workloads"][name][eng]["error_vs_oracle"] = e
     print(json.dumps(line))
 
 

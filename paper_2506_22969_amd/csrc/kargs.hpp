@@ -79,6 +79,11 @@ MmaLaunch find_mma3d(const MmaKey &key);
 bool mma3d_geometry(const MmaKey &key, int *wgh, int *row);
 int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max);
 
+// Dense FP64 MMA sweep (tile 8 x 4, FP64 state and coefficients): the
+// launch for radius `rad` and KC chunks of 4, and its slab row pitch.
+MmaLaunch find_mma2d_f64(int rad, int kc);
+int mma2d_f64_pitch(int rad);
+
 // Fills total_blocks and the jobs' block0 from their grid sizes.
 hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s);
 

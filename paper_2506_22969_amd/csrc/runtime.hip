@@ -376,6 +376,61 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     return SS_OK;
 }
 
+// Dense FP64 MMA engine (2-D): A' in FP64, natural column order, one tile
+// shape (8,4); gather offsets per K chunk and lane group.
+ss_status plan_mma2d_f64(ss_plan_ *p) {
+    const int r1 = 8, r2 = 4;
+    if (p->info.r1 && (p->info.r1 != r1 || p->info.r2 != r2)) return SS_E_UNSUPPORTED;
+    const Geometry gm = make_geometry(2, p->k, r1, r2);
+    const int kp = gm.k_prime(), kc_count = (kp + 3) / 4, MB = gm.m_prime() / 16;
+    const MmaLaunch fn = find_mma2d_f64(p->rad, kc_count);
+    const int pitch = mma2d_f64_pitch(p->rad);
+    if (!fn || pitch == 0) return SS_E_UNSUPPORTED;
+    const std::vector<double> amat = morph_matrix(gm, p->w);
+    std::vector<double> a((size_t)MB * kc_count * 64, 0.0);
+    for (int mb = 0; mb < MB; ++mb)
+        for (int kc = 0; kc < kc_count; ++kc)
+            for (int l = 0; l < 64; ++l) {
+                const int row = mb * 16 + (l & 15), col = kc * 4 + (l >> 4);
+                a[((size_t)mb * kc_count + kc) * 64 + l] = col < kp ? amat[(size_t)row * kp + col] : 0.0;
+            }
+    std::vector<int32_t> boff((size_t)kc_count * 4, 0);
+    for (int kc = 0; kc < kc_count; ++kc)
+        for (int q = 0; q < 4; ++q) {
+            const int col = kc * 4 + q;
+            boff[(size_t)kc * 4 + q] = col < kp ? (col / gm.g) * pitch + col % gm.g : 0;
+        }
+    p->perm.clear();
+    for (int c = 0; c < kc_count * 4; ++c) p->perm.push_back(c < kp ? c : kZeta);
+    p->kernel_lut = boff;
+    auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_b = align(a.size() * 8), o_z = align(o_b + boff.size() * 4);
+    std::vector<uint8_t> blob(o_z + 1024, 0);
+    std::memcpy(blob.data(), a.data(), a.size() * 8);
+    std::memcpy(blob.data() + o_b, boff.data(), boff.size() * 4);
+    ss_status st = upload(p, blob);
+    if (st != SS_OK) return st;
+    char *d = static_cast<char *>(p->dev);
+    p->mma = fn;
+    p->margs.periodic = p->boundary == SS_BC_PERIODIC;
+    p->margs.inv_sigma = 1.0f;
+    p->margs.a_hi = reinterpret_cast<const uint4 *>(d);
+    p->margs.boff = reinterpret_cast<const int32_t *>(d + o_b);
+    p->margs.zeros = d + o_z;
+    p->engine = SS_ENGINE_MFMA;
+    p->info.r1 = r1;
+    p->info.r2 = r2;
+    p->info.m_b = gm.m_b;
+    p->info.g = gm.g;
+    p->info.planes = gm.planes;
+    p->info.m_prime = gm.m_prime();
+    p->info.k_prime = kp;
+    p->info.k_pad = kc_count * 4;
+    p->info.passes = 1;
+    p->info.sigma = 1.0;
+    return SS_OK;
+}
+
 ss_status plan_direct(ss_plan_ *p) {
     const bool f64 = p->dtype == SS_F64;
     std::vector<uint8_t> blob(p->w.size() * (f64 ? 8 : 4));
@@ -480,6 +535,8 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
         if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma3d(p, SS_ENGINE_MFMA);
     } else if (split3 && ndim == 3 && engine == SS_ENGINE_MFMA) {
         st = plan_mma3d(p, SS_ENGINE_MFMA);
+    } else if (dtype == SS_F64 && ndim == 2 && engine == SS_ENGINE_MFMA) {
+        st = plan_mma2d_f64(p);
     }
     if (st != SS_OK && (engine == SS_ENGINE_DIRECT || engine == SS_ENGINE_AUTO) &&
         (dtype == SS_F32 || dtype == SS_F64 || split) && o.r1 == 0)

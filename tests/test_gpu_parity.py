@@ -100,6 +100,23 @@ def test_star5_heat2d_f64_direct_c1():
     assert normwise_err(got, ref) <= 1e-13
 
 
+@pytest.mark.parametrize("dims", [(256, 256), (129, 131), (7, 5), (300, 520)])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_f64_mfma_engine(dims, boundary):
+    # FP64 staircase product on v_mfma_f64_16x16x4: Heat-2D and a random
+    # 9-point box, 10 sweeps, against the oracle at the FP64 bound
+    x0 = synthetic.grid_f64(dims, seed=2)
+    for shape, w in [("star", synthetic.heat2d_coeffs()),
+                     ("box", synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)[0])]:
+        with native.Plan(shape, 1, w, dims, "f64", boundary=boundary, engine="mfma") as p:
+            assert p.info["engine_name"] == "mfma"
+            got = run_plan(p, x0, 10)
+        ref = oracle_direct.run(x0, w, 10, periodic=(boundary == "periodic"))
+        err = normwise_err(got, ref)
+        print(f"f64 mfma {shape} {dims} {boundary} err={err:.3e}")
+        assert err <= 1e-13
+
+
 @pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
 def test_constant_field_bit_exact(engine):
     # Heat-2D coefficients and the state 0.75 are binary16 numbers; every
