@@ -45,6 +45,8 @@ def parse():
                     help="Poisson arrival rate as a fraction of the measured batch capacity")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
+    ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p"],
+                    help="only run four sweeps of one workload on the sparse engine (for profilers)")
     return ap.parse_args()
 
 
@@ -346,11 +348,47 @@ def serving_leg(native, torch, n_jobs: int, load: float):
     }
 
 
+def profile_only(name: str):
+    """Four sweeps of one workload on the sparse engine, nothing else: a short
+    program for counter collection."""
+    import torch
+
+    import synthetic
+    from paper_2506_22969_amd import native
+
+    stream = torch.cuda.current_stream()
+    if name == "box2d9p":
+        w = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(NY, NX))[0]
+        x = torch.from_numpy(synthetic.grid_f32((NY, NX), seed=0)).to("cuda:0")
+        plan = native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac")
+    elif name == "box2d49p_planes":
+        w = synthetic.random_coeffs("box", 3, 2, seed=277, grid_shape=(8192, 8192))[0]
+        bits = synthetic.grid_bf16_planes((8192, 8192), seed=0)
+        x = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
+        plan = native.Plan("box", 3, w, (8192, 8192), "split_bf16", boundary="periodic", fuse_steps=2,
+                           engine="smfmac")
+    else:
+        w = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
+        x = torch.from_numpy(synthetic.grid_f32((512, 512, 512), seed=0)).to("cuda:0")
+        plan = native.Plan("box", 1, w, (512, 512, 512), "f32_split_f16", engine="smfmac")
+    y = torch.empty_like(x)
+    for _ in range(4):
+        plan.sweep(x, y, stream.cuda_stream)
+        x, y = y, x
+    torch.cuda.synchronize()
+    info = plan.info
+    plan.close()
+    print(json.dumps({"profile": name, "tile": [info["r1"], info["r2"]], "k_pad": info["k_pad"]}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.profile:
+        profile_only(args.profile)
+        return
     import torch
 
     import synthetic

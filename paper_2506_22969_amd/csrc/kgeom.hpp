@@ -21,11 +21,18 @@ enum State { kStateF32 = 0, kStatePlanes = 1 };
 template <int R1, int R2, int RAD, int STATE>
 struct MmaGeom {
     static constexpr int MB = R1 * R2 / 16;            // 16-row M-blocks of A'
-    static constexpr int NBX = 128 / R1;               // tiles of a unit along x
+    // Tiles of a unit along x: a 128-column unit, except 16-wide tiles on
+    // the planes state, whose units are 4 tiles across and 4 tile rows down
+    // (with the row pitch below, the 16 tiles then start in 16 different
+    // LDS banks)
+    static constexpr bool SQUARE = STATE == kStatePlanes && R1 == 16;
+    static constexpr int NBX = SQUARE ? 4 : 128 / R1;
     static constexpr int NBY = 16 / NBX;               // ... along y
     static constexpr int NBH = NBY * R2;               // rows of a unit
-    static constexpr int U = kItemRows / (kWaves / kNbCols * NBH);  // units per wave
-    static constexpr int WGH = kWaves / kNbCols * U * NBH;          // rows of a work item
+    static constexpr int UW = NBX * R1;                // columns of a unit
+    static constexpr int NCOLS = kBandX / UW;          // units across a band
+    static constexpr int U = kItemRows / (kWaves / NCOLS * NBH);  // units per wave
+    static constexpr int WGH = kWaves / NCOLS * U * NBH;          // rows of a work item
     static_assert(WGH == kItemRows, "tile does not divide the work item");
     static constexpr int SROWS = WGH + 2 * RAD;        // slab rows
     // FP32 slab rows (floats): HL columns of left margin (>= RAD, a multiple
@@ -36,15 +43,20 @@ struct MmaGeom {
     // Planes slab (bfloat16 elements): a hi part of SROWS rows of PB
     // elements, then a lo part of the same shape (LO elements further on).
     // Rows have an 8-element left margin and up to 8 right halo columns;
-    // halo columns move in pairs (HD dwords per side and plane).  PB/2 dwords
-    // is 4 mod 8, so that vertically adjacent tiles start in different LDS
-    // banks; PB is a multiple of 8 so that every row starts 16-byte aligned.
+    // halo columns move in pairs (HD dwords per side and plane).  With
+    // 16-wide tiles (8 dwords apart along a row, 4 per unit row) the pitch
+    // makes the 4 tile rows of a unit start 2 dwords apart modulo 8:
+    // R2 * PB / 2 = 2 (mod 8).  A pitch that is a multiple of 8 keeps every
+    // row 16-byte aligned (LDS DMA in 16-byte pieces); otherwise rows move
+    // in 4-byte pieces.
     static constexpr int HLB = 8;
-    static constexpr int PB = 280;
+    static constexpr int PB = !SQUARE ? 280 : R2 == 1 ? 276 : 274;
+    static constexpr bool PLANES_X4 = PB % 8 == 0;
     static constexpr int LO = SROWS * PB;
     static constexpr int HD = (RAD + 1) / 2;
     static_assert(STATE == kStateF32 || 2 * HD <= HLB, "halo wider than the margin");
-    static_assert(PB >= HLB + kBandX + 2 * HD && PB % 8 == 0 && (PB / 2) % 8 == 4, "plane row pitch");
+    static_assert(PB >= HLB + kBandX + 2 * HD && PB % 2 == 0, "plane row pitch");
+    static_assert(!SQUARE || (R2 * PB / 2) % 8 == 2, "plane row pitch does not spread the banks");
     // with an even radius every B register's two values share one dword
     // (tile origins and pair columns are even)
     static constexpr bool PAIR_DWORD = STATE == kStatePlanes && RAD % 2 == 0;

@@ -139,7 +139,8 @@ struct Pipe {
     // LDS-DMA operations per slab row: FP32 one 16-byte transfer per lane
     // (or four 4-byte ones when rows are not 16-byte aligned); planes one
     // 16-byte transfer per half wave and plane
-    static constexpr int DMA_PER_ROW = STATE == kStatePlanes ? 2 : (VEC ? 1 : kBandX / 64);
+    static constexpr int DMA_PER_ROW =
+        STATE == kStatePlanes ? (G::PLANES_X4 ? 2 : 2 * kBandX / 128) : (VEC ? 1 : kBandX / 64);
     static constexpr int D = DRW * DMA_PER_ROW + G::HOPS;               // VMEM loads per wave per item
     static constexpr int STORES_PER_MB = STATE == kStatePlanes ? 2 : (VEC ? 1 : 4);
     static constexpr int M = G::U * G::MB * STORES_PER_MB;              // VMEM stores per wave per item
@@ -209,9 +210,23 @@ __device__ inline void issue_item(const MmaArgs &p, const MmaJob &g, char *slab,
             const unsigned short *srow = reinterpret_cast<const unsigned short *>(slab) + r * G::PB + G::HLB;
             const unsigned dst_hi = lds_addr_of(srow);
             const unsigned dst_lo = lds_addr_of(srow + G::LO);
-            // lanes 32..63 land at M0 + 16*lane, i.e. 512 bytes past M0
-            if (half == 0) lds_dma16(src, dst_hi);
-            else lds_dma16(src, dst_lo - 512);
+            if constexpr (G::PLANES_X4) {
+                // lanes 32..63 land at M0 + 16*lane, i.e. 512 bytes past M0
+                if (half == 0) lds_dma16(src, dst_hi);
+                else lds_dma16(src, dst_lo - 512);
+            } else {
+                // 4-byte pieces: two values per lane, 128 values per transfer
+#pragma unroll
+                for (int pl = 0; pl < 2; ++pl)
+#pragma unroll
+                    for (int h = 0; h < kBandX / 128; ++h) {
+                        const int gx2 = wrap<BC>(X0 + 128 * h + 2 * lane, g.nx);
+                        const bool ok2 = BC != kBcZero || (row_ok && gx2 < g.nx);
+                        const void *src2 = ok2 ? (const void *)(in + pl * plane + (size_t)gy * g.nx + gx2)
+                                               : (const void *)(zeros + 4 * lane);
+                        lds_dma4(src2, (pl ? dst_lo : dst_hi) + 256 * h);
+                    }
+            }
         } else {
             const float *in = static_cast<const float *>(g.in);
             const float *zf = reinterpret_cast<const float *>(zeros);
@@ -288,7 +303,8 @@ __device__ inline int gather_off(const unsigned (&o2)[VPK / 2], int v) {
 }
 
 // Multiply one work item out of its LDS slab and write its outputs.  Wave w
-// owns units (w / 2) * U + u of column w % 2: 16 tiles of R2 x R1 outputs each.
+// owns units (w / NCOLS) * U + u of unit column w % NCOLS: 16 tiles of
+// R2 x R1 outputs each.
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE, bool VEC>
 __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const char *slab,
                                     const uint4 (&ahi)[R1 * R2 / 16][KC], const uint4 (&alo)[R1 * R2 / 16][KC],
@@ -300,8 +316,8 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int nb = wave / kNbCols;            // unit row group of the item
-    const int nbc = wave % kNbCols;           // unit column of the band
+    const int nb = wave / G::NCOLS;           // unit row group of the item
+    const int nbc = wave % G::NCOLS;          // unit column of the band
     const int n = lane & 15;
     const int q = lane >> 4;
     const int tx_t = n % G::NBX;
@@ -310,7 +326,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
     X0 = __builtin_amdgcn_readfirstlane(X0);
     Y0 = __builtin_amdgcn_readfirstlane(Y0);
     const int rows_left = min(G::WGH, g.ny - Y0);
-    const int xbase = X0 + nbc * 128 + tx_t * R1;
+    const int xbase = X0 + nbc * G::UW + tx_t * R1;
 #pragma unroll 1
     for (int u = 0; u < G::U; ++u) {
         const int urow = (nb * G::U + u) * G::NBH;   // first row of the unit in the item
@@ -326,7 +342,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
             unsigned bh[VPK], bl[VPK];
             if constexpr (STATE == kStatePlanes) {
                 // element index of the tile's patch origin in the hi rows
-                const int tb = srow0 * G::ROW + (G::HLB - RAD) + nbc * 128 + tx_t * R1;
+                const int tb = srow0 * G::ROW + (G::HLB - RAD) + nbc * G::UW + tx_t * R1;
                 const unsigned *s32 = reinterpret_cast<const unsigned *>(slab);
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
@@ -343,7 +359,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
                 }
             } else {
                 const float *tb = reinterpret_cast<const float *>(slab) + srow0 * G::CPITCH + (G::HL - RAD) +
-                                  nbc * 128 + tx_t * R1;
+                                  nbc * G::UW + tx_t * R1;
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
                     const float *src = tb + gather_off<VPK>(off2[kc], v);

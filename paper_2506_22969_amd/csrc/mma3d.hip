@@ -7,8 +7,11 @@
 // columns never share a 4-group here), and every plane's K columns are
 // padded to whole MMA chunks, so that a chunk gathers from a single input
 // plane.  A work item is a 256 x WGH column of the grid over ZC planes; the
-// workgroup marches through z keeping a ring of input planes in LDS, filled
-// by LDS DMA several planes ahead of the plane being multiplied.
+// workgroup streams the input planes through a ring of LDS slabs filled by
+// LDS DMA several planes ahead.  Each input plane is gathered into B
+// registers once and multiplied by the A blocks of all 2r+1 plane offsets,
+// accumulating into the 2r+1 output planes it contributes to; the oldest of
+// those is complete after the plane and is stored.
 #include <hip/hip_runtime.h>
 
 #include "mma2d_impl.hpp"
@@ -22,25 +25,31 @@ struct Pipe3 {
     static constexpr int DMA_PER_ROW = VEC ? 1 : kBandX / 64;
     static constexpr int D1 = DRW * DMA_PER_ROW;                   // VMEM loads per plane, waves 1..7
     static constexpr int D0 = D1 + G::HOPS;                        // ... wave 0 (also the halo)
-    static constexpr int M = G::MB * (VEC ? 1 : 4);                // VMEM stores per plane
-    static constexpr int A = 2 * RAD;                              // planes needed beyond the current
-    // VMEM operations issued after load t+A when step t consumes it (loads
-    // 0..NP-2 are issued before step 0 and step t issues load t+NP-1 before
-    // its stores)
-    template <int D, int T>
-    static constexpr int W = (G::NP - 2 - A) * D + (T < G::NP - 1 - A ? T : G::NP - 1 - A) * M;
+    static constexpr int M = G::MB * (VEC ? 1 : 4);                // VMEM stores per output plane
+    static constexpr int A = 2 * RAD;                              // steps before the first store
+    // VMEM operations issued after load p when step p consumes it: loads
+    // 0..NP-2 are issued before step 0, step j issues load j+NP-1 and then,
+    // from step A on, the stores of one output plane; S = min(max(p-A, 0),
+    // NP-1) counts the steps with stores among those that follow load p
+    template <int D, int S>
+    static constexpr int W = (G::NP - 2) * D + S * M;
 };
 
 template <int D, int R1, int R2, int RAD, bool VEC>
-__device__ inline void wait_step3(int t) {
+__device__ inline void wait_step3(int p) {
     using P = Pipe3<R1, R2, RAD, VEC>;
-    switch (t) {
+    constexpr int NP = Mma3Geom<R1, R2, RAD>::NP;
+    const int st = min(max(p - P::A, 0), NP - 1);
+    static_assert(NP <= 8, "wait table covers up to 8 ring slots");
+    switch (st) {
         case 0: wait_vmcnt<P::template W<D, 0>>(); break;
         case 1: wait_vmcnt<P::template W<D, 1>>(); break;
         case 2: wait_vmcnt<P::template W<D, 2>>(); break;
         case 3: wait_vmcnt<P::template W<D, 3>>(); break;
         case 4: wait_vmcnt<P::template W<D, 4>>(); break;
-        default: wait_vmcnt<P::template W<D, 5>>(); break;
+        case 5: wait_vmcnt<P::template W<D, 5>>(); break;
+        case 6: wait_vmcnt<P::template W<D, 6>>(); break;
+        default: wait_vmcnt<P::template W<D, 7>>(); break;
     }
 }
 
@@ -109,8 +118,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     constexpr int MB = G::MB;
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
     constexpr int NP = G::NP;
-    constexpr int CPP = KC / (2 * RAD + 1);  // K chunks per input plane
-    static_assert(CPP * (2 * RAD + 1) == KC, "chunks must not straddle planes");
+    constexpr int NZ = 2 * RAD + 1;          // plane offsets of the stencil
+    constexpr int CPP = KC / NZ;             // K chunks per input plane
+    static_assert(CPP * NZ == KC, "chunks must not straddle planes");
     __shared__ __attribute__((aligned(16))) char lds[NP * G::SLOT];
     auto slab = [&](int i) { return lds + i * G::PLANE_BYTES; };
     auto strip = [&](int i) { return reinterpret_cast<unsigned *>(lds + NP * G::PLANE_BYTES) + i * G::HSTRIP; };
@@ -129,13 +139,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int q = lane >> 4;
-    unsigned off2[KC][VPK / 2];
+    // every plane has the same K order (shifted by whole planes), so the
+    // gather offsets of its CPP chunks serve all plane offsets
+    unsigned off2[CPP][VPK / 2];
 #pragma unroll
-    for (int kc = 0; kc < KC; ++kc)
+    for (int c = 0; c < CPP; ++c)
 #pragma unroll
         for (int v = 0; v < VPK; v += 2)
-            off2[kc][v / 2] = (unsigned)p.boff[(kc * 4 + q) * VPK + v] |
-                              ((unsigned)p.boff[(kc * 4 + q) * VPK + v + 1] << 16);
+            off2[c][v / 2] = (unsigned)p.boff[(c * 4 + q) * VPK + v] |
+                             ((unsigned)p.boff[(c * 4 + q) * VPK + v + 1] << 16);
     uint4 ahi[MB][KC], alo[MB][KC];
     unsigned aidx[MB][KC];
 #pragma unroll
@@ -167,77 +179,95 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
         const int Y0 = (local % nrb) * G::WGH;
         const int z0 = (local / nrb) * g.zc;
         const int nzc = min(g.zc, g.nz - z0);
-        const int last = nzc + 2 * RAD - 1;  // last load of the item
+        const int nload = nzc + 2 * RAD;   // input planes z0-RAD .. z0+nzc-1+RAD
         auto issue = [&](int l) {
-            const int zz = wrap<BC>(z0 - RAD + min(l, last), g.nz);
+            const int zz = wrap<BC>(z0 - RAD + min(l, nload - 1), g.nz);
             issue_plane<R1, R2, RAD, VEC, BC>(p, g, slab(l % NP), strip(l % NP), X0, Y0, zz);
         };
 #pragma unroll 1
         for (int l = 0; l < NP - 1; ++l) issue(l);
         const int rows_left = min(G::WGH, g.ny - Y0);
         const int xbase = X0 + nbc * 128 + tx_t * R1;
-#pragma unroll 1
-        for (int t = 0; t < nzc; ++t) {
-            if (wave == 0) wait_step3<P::D0, R1, R2, RAD, VEC>(t);
-            else wait_step3<P::D1, R1, R2, RAD, VEC>(t);
-            __builtin_amdgcn_s_barrier();
-            if (t == 0) {
-                for (int l = 0; l <= 2 * RAD; ++l) put_halo3<R1, R2, RAD>(slab(l % NP), strip(l % NP));
-            } else {
-                put_halo3<R1, R2, RAD>(slab((t + 2 * RAD) % NP), strip((t + 2 * RAD) % NP));
-            }
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            __builtin_amdgcn_s_barrier();
-            issue(t + NP - 1);
-            // multiply output plane z0 + t
-            f4 accm[MB], accc[MB];
+        // acc[i] accumulates output plane z0 + (l - 2*RAD + i) at step l
+        f4 accm[NZ][MB], accc[NZ][MB];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                accm[mb] = f4{0.f, 0.f, 0.f, 0.f};
-                accc[mb] = f4{0.f, 0.f, 0.f, 0.f};
+                accm[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                accc[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
+#pragma unroll 1
+        for (int l = 0; l < nload; ++l) {
+            if (wave == 0) wait_step3<P::D0, R1, R2, RAD, VEC>(l);
+            else wait_step3<P::D1, R1, R2, RAD, VEC>(l);
+            __builtin_amdgcn_s_barrier();
+            put_halo3<R1, R2, RAD>(slab(l % NP), strip(l % NP));
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_s_barrier();
+            issue(l + NP - 1);
+            // input plane l: once into B registers, times every plane offset
+            const float *tb = reinterpret_cast<const float *>(slab(l % NP)) + srow0 * G::CPITCH + (G::HL - RAD) +
+                              nbc * 128 + tx_t * R1;
 #pragma unroll
-            for (int kc = 0; kc < KC; ++kc) {
-                const int pz = kc / CPP;
-                const float *tb = reinterpret_cast<const float *>(slab((t + pz) % NP)) + srow0 * G::CPITCH +
-                                  (G::HL - RAD) + nbc * 128 + tx_t * R1;
+            for (int c = 0; c < CPP; ++c) {
                 unsigned bh[VPK], bl[VPK];
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const float *src = tb + gather_off<VPK>(off2[kc], v);
+                    const float *src = tb + gather_off<VPK>(off2[c], v);
                     split2<PART>(src[0], src[1], sigma, &bh[v], &bl[v]);
                 }
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    accm[mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[mb], aidx[mb][kc]);
-                    accc[mb] = mma<MODE, PART>(ahi[mb][kc], bl, accc[mb], aidx[mb][kc]);
-                    accc[mb] = mma<MODE, PART>(alo[mb][kc], bh, accc[mb], aidx[mb][kc]);
-                }
+                for (int pz = 0; pz < NZ; ++pz)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        const int kc = pz * CPP + c;
+                        f4 &am = accm[NZ - 1 - pz][mb];
+                        f4 &ac = accc[NZ - 1 - pz][mb];
+                        am = mma<MODE, PART>(ahi[mb][kc], bh, am, aidx[mb][kc]);
+                        ac = mma<MODE, PART>(ahi[mb][kc], bl, ac, aidx[mb][kc]);
+                        ac = mma<MODE, PART>(alo[mb][kc], bh, ac, aidx[mb][kc]);
+                    }
             }
-            float *out = static_cast<float *>(g.out) + ((size_t)(z0 + t) * g.ny + Y0) * g.nx;
-            const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
+            // output plane z0 + l - 2*RAD is complete
+            if (l >= 2 * RAD) {
+                float *out = static_cast<float *>(g.out) + ((size_t)(z0 + l - 2 * RAD) * g.ny + Y0) * g.nx;
+                const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const int o = mb * 16 + 4 * q;
-                const int gyr = srow0 + o / R1;
-                const int gx = xbase + o % R1;
-                float ys[4];
+                for (int mb = 0; mb < MB; ++mb) {
+                    const int o = mb * 16 + 4 * q;
+                    const int gyr = srow0 + o / R1;
+                    const int gx = xbase + o % R1;
+                    float ys[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) ys[i] = accm[mb][i] + accc[mb][i] * p.inv_sigma;
-                const bool row_ok = gyr < rows_left;
-                if constexpr (VEC) {
-                    const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
-                                    __float_as_uint(ys[3])};
-                    const unsigned o4 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
-                    __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o4, 0, 0);
-                } else {
+                    for (int i = 0; i < 4; ++i) ys[i] = accm[0][mb][i] + accc[0][mb][i] * p.inv_sigma;
+                    const bool row_ok = gyr < rows_left;
+                    if constexpr (VEC) {
+                        const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
+                                        __float_as_uint(ys[3])};
+                        const unsigned o4 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
+                        __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o4, 0, 0);
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const unsigned o1 =
-                            row_ok && gx + i < g.nx ? (unsigned)(gyr * g.nx + gx + i) * 4u : kOob;
-                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc, o1, 0, 0);
+                        for (int i = 0; i < 4; ++i) {
+                            const unsigned o1 =
+                                row_ok && gx + i < g.nx ? (unsigned)(gyr * g.nx + gx + i) * 4u : kOob;
+                            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc, o1, 0, 0);
+                        }
                     }
                 }
+            }
+#pragma unroll
+            for (int i = 0; i + 1 < NZ; ++i)
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    accm[i][mb] = accm[i + 1][mb];
+                    accc[i][mb] = accc[i + 1][mb];
+                }
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                accm[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                accc[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
         }
         // the ring is refilled by the next item: let this item's transfers

@@ -55,16 +55,23 @@ def test_server_mix_matches_run_alone():
         (w9, (129, 131), "f32_split_f16", "mfma", "periodic", 4),
         (w9, (256, 1024), "f32_split_bf16", "smfmac", "periodic", 9),
         (w9, (200, 300), "f32", "direct", "zero", 6),
-        (w9b, (96, 64, 80), None, "direct", "periodic", 3),
+        ("3d", (96, 64, 80), "f32", "direct", "periodic", 3),
+        ("3d", (40, 48, 264), "f32_split_f16", "smfmac", "zero", 5),
+        ("3d", (24, 48, 264), "f32_split_f16", "smfmac", "zero", 4),
+        (w9, (64, 264), "split_bf16", "smfmac", "periodic", 3),
+        (w9, (96, 264), "split_bf16", "smfmac", "periodic", 6),
     ]
     plans, jobs = [], []
+    w3 = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
     for i, (w, dims, dtype, engine, bc, steps) in enumerate(specs):
-        if len(dims) == 3:  # 3-D box of radius 1 built from the 2-D draw
-            w = synthetic.random_coeffs("box", 1, 3, seed=70, grid_shape=dims)[0]
-            dtype = "f32"
+        if len(dims) == 3:  # 3-D box of radius 1
+            w = w3
         plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine)
         plans.append(plan)
-        x0 = torch.from_numpy(synthetic.grid_f32(dims, seed=10 + i)).to(dev)
+        if dtype == "split_bf16":
+            x0 = torch.from_numpy(synthetic.grid_bf16_planes(dims, seed=10 + i).view(np.int16)).to(dev)
+        else:
+            x0 = torch.from_numpy(synthetic.grid_f32(dims, seed=10 + i)).to(dev)
         jobs.append((plan, x0, steps))
 
     # reference: each job alone through sparstencil_run
@@ -80,7 +87,7 @@ def test_server_mix_matches_run_alone():
     largest = max(p.grid_bytes for p, _, _ in jobs)
     arena_bytes = 3 * ((largest + 255) // 256 * 256)
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
-    outs = [torch.full_like(x0, float("nan")) for _, x0, _ in jobs]
+    outs = [torch.full_like(x0, -1) for _, x0, _ in jobs]
     with native.Server(arena, arena_bytes, max_jobs=64, num_streams=3) as srv:
         ids = [srv.submit(plan, x0, out, steps) for (plan, x0, steps), out in zip(jobs, outs)]
         srv.drain()
