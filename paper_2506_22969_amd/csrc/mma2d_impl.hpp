@@ -291,7 +291,8 @@ __device__ inline void put_halo(char *slab, const unsigned *strip) {
     }
 }
 
-// Gather offset of B register v of a K chunk: two 16-bit offsets per word.
+// Gather offset (bytes) of B register v of a K chunk: two 16-bit offsets
+// per word.
 // The empty asm hides the word's value from the optimiser, so that the
 // unpacked offsets are not hoisted out of the item loop and kept live (which
 // would undo the packing).
@@ -331,47 +332,54 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
     for (int u = 0; u < G::U; ++u) {
         const int urow = (nb * G::U + u) * G::NBH;   // first row of the unit in the item
         const int srow0 = urow + ty_t * R2;          // tile's first row (slab rows start RAD above)
-        f4 accm[MB], accc[MB];
+        // hi*hi, hi*lo and lo*hi accumulate separately (no back-to-back
+        // dependent MMAs)
+        f4 accm[MB], acc1[MB], acc2[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             accm[mb] = f4{0.f, 0.f, 0.f, 0.f};
-            accc[mb] = f4{0.f, 0.f, 0.f, 0.f};
+            acc1[mb] = f4{0.f, 0.f, 0.f, 0.f};
+            acc2[mb] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        // byte address of the tile's patch origin in the slab (hi rows for
+        // the planes state); gather offsets are in bytes from it
+        constexpr int ES = STATE == kStatePlanes ? 2 : 4;
+        const int tbo = (srow0 * G::ROW + (G::MARGIN - RAD) + nbc * G::UW + tx_t * R1) * ES;
+        const char *tb = slab + tbo;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
             unsigned bh[VPK], bl[VPK];
             if constexpr (STATE == kStatePlanes) {
-                // element index of the tile's patch origin in the hi rows
-                const int tb = srow0 * G::ROW + (G::HLB - RAD) + nbc * G::UW + tx_t * R1;
-                const unsigned *s32 = reinterpret_cast<const unsigned *>(slab);
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const int e = tb + gather_off<VPK>(off2[kc], v);
-                    const unsigned *w = s32 + (e >> 1);
                     if constexpr (G::PAIR_DWORD) {
+                        const unsigned *w = reinterpret_cast<const unsigned *>(tb + gather_off<VPK>(off2[kc], v));
                         bh[v] = w[0];
                         bl[v] = w[G::LO / 2];
                     } else {
-                        const unsigned sh = (unsigned)(e & 1) * 2u;
+                        // the pair may start at an odd value: two dwords and
+                        // a byte align (offset arithmetic stays relative to
+                        // the slab, so the reads remain LDS reads)
+                        const int ai = tbo + gather_off<VPK>(off2[kc], v);
+                        const unsigned *w = reinterpret_cast<const unsigned *>(slab + (ai & ~3));
+                        const unsigned sh = (unsigned)(ai & 2);
                         bh[v] = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
                         bl[v] = __builtin_amdgcn_alignbyte(w[G::LO / 2 + 1], w[G::LO / 2], sh);
                     }
                 }
             } else {
-                const float *tb = reinterpret_cast<const float *>(slab) + srow0 * G::CPITCH + (G::HL - RAD) +
-                                  nbc * G::UW + tx_t * R1;
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const float *src = tb + gather_off<VPK>(off2[kc], v);
+                    const float *src = reinterpret_cast<const float *>(tb + gather_off<VPK>(off2[kc], v));
                     split2<PART>(src[0], src[1], sigma, &bh[v], &bl[v]);
                 }
             }
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                accm[mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[mb], aidx[mb][kc]);
-                accc[mb] = mma<MODE, PART>(ahi[mb][kc], bl, accc[mb], aidx[mb][kc]);
-                accc[mb] = mma<MODE, PART>(alo[mb][kc], bh, accc[mb], aidx[mb][kc]);
-            }
+            for (int mb = 0; mb < MB; ++mb) accm[mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[mb], aidx[mb][kc]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc1[mb] = mma<MODE, PART>(ahi[mb][kc], bl, acc1[mb], aidx[mb][kc]);
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) acc2[mb] = mma<MODE, PART>(alo[mb][kc], bh, acc2[mb], aidx[mb][kc]);
         }
         // write back: accumulator rows 4q..4q+3 of M-block mb are outputs
         // mb*16 + 4q + i of the tile, four consecutive x positions.  Buffer
@@ -384,7 +392,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
             const int gx = xbase + o % R1;
             float ys[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ys[i] = accm[mb][i] + accc[mb][i] * p.inv_sigma;
+            for (int i = 0; i < 4; ++i) ys[i] = accm[mb][i] + (acc1[mb][i] + acc2[mb][i]) * p.inv_sigma;
             const bool row_ok = gyr < rows_left;
             if constexpr (STATE == kStatePlanes) {
                 // bfloat16 hi = RNE(y), lo = RNE(y - hi); rows are a
@@ -461,7 +469,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
 
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4;
-    // gather offsets (below 2^16 elements for every instantiated geometry)
+    // gather offsets (below 2^16 bytes for every instantiated geometry)
     unsigned off2[KC][VPK / 2];
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc)

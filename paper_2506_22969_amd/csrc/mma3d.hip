@@ -189,13 +189,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
         const int rows_left = min(G::WGH, g.ny - Y0);
         const int xbase = X0 + nbc * 128 + tx_t * R1;
         // acc[i] accumulates output plane z0 + (l - 2*RAD + i) at step l
-        f4 accm[NZ][MB], accc[NZ][MB];
+        // hi*hi, hi*lo and lo*hi accumulate separately
+        f4 accm[NZ][MB], acc1[NZ][MB], acc2[NZ][MB];
 #pragma unroll
         for (int i = 0; i < NZ; ++i)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 accm[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                accc[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc1[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc2[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll 1
         for (int l = 0; l < nload; ++l) {
@@ -207,26 +209,24 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
             __builtin_amdgcn_s_barrier();
             issue(l + NP - 1);
             // input plane l: once into B registers, times every plane offset
-            const float *tb = reinterpret_cast<const float *>(slab(l % NP)) + srow0 * G::CPITCH + (G::HL - RAD) +
-                              nbc * 128 + tx_t * R1;
+            const char *tb =
+                slab(l % NP) + (srow0 * G::CPITCH + (G::HL - RAD) + nbc * 128 + tx_t * R1) * 4;
 #pragma unroll
             for (int c = 0; c < CPP; ++c) {
                 unsigned bh[VPK], bl[VPK];
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const float *src = tb + gather_off<VPK>(off2[c], v);
+                    const float *src = reinterpret_cast<const float *>(tb + gather_off<VPK>(off2[c], v));
                     split2<PART>(src[0], src[1], sigma, &bh[v], &bl[v]);
                 }
 #pragma unroll
                 for (int pz = 0; pz < NZ; ++pz)
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
-                        const int kc = pz * CPP + c;
-                        f4 &am = accm[NZ - 1 - pz][mb];
-                        f4 &ac = accc[NZ - 1 - pz][mb];
-                        am = mma<MODE, PART>(ahi[mb][kc], bh, am, aidx[mb][kc]);
-                        ac = mma<MODE, PART>(ahi[mb][kc], bl, ac, aidx[mb][kc]);
-                        ac = mma<MODE, PART>(alo[mb][kc], bh, ac, aidx[mb][kc]);
+                        const int kc = pz * CPP + c, i = NZ - 1 - pz;
+                        accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[i][mb], aidx[mb][kc]);
+                        acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl, acc1[i][mb], aidx[mb][kc]);
+                        acc2[i][mb] = mma<MODE, PART>(alo[mb][kc], bh, acc2[i][mb], aidx[mb][kc]);
                     }
             }
             // output plane z0 + l - 2*RAD is complete
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                     const int gx = xbase + o % R1;
                     float ys[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ys[i] = accm[0][mb][i] + accc[0][mb][i] * p.inv_sigma;
+                    for (int i = 0; i < 4; ++i) ys[i] = accm[0][mb][i] + (acc1[0][mb][i] + acc2[0][mb][i]) * p.inv_sigma;
                     const bool row_ok = gyr < rows_left;
                     if constexpr (VEC) {
                         const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
@@ -262,12 +262,14 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     accm[i][mb] = accm[i + 1][mb];
-                    accc[i][mb] = accc[i + 1][mb];
+                    acc1[i][mb] = acc1[i + 1][mb];
+                    acc2[i][mb] = acc2[i + 1][mb];
                 }
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 accm[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                accc[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc1[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc2[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
         }
         // the ring is refilled by the next item: let this item's transfers

@@ -1,8 +1,10 @@
-// Serving loop: admits stencil jobs as they arrive (sized by a device arena),
-// keeps their grids resident between sweeps and advances all running jobs in
-// rounds; jobs whose plans share device tables are swept by one launch per
-// round, different plan classes run on different streams so their launches
-// overlap on the device.
+// Serving loop: admits stencil jobs as they arrive (sized by a device arena)
+// and keeps their grids resident between sweeps.  Jobs whose plans share
+// device tables (one plan class) are swept together, up to 16 grids per
+// launch; each class advances on its own stream as soon as its previous
+// launch has finished, so classes with short sweeps are not held back by
+// classes with long ones, and a job that arrives joins its class's next
+// launch.  The worker thread never blocks on the device: it polls events.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +51,9 @@ class Arena {
     std::map<size_t, size_t> used_;  // offset -> bytes
 };
 
+// Device work of a job in flight: admission copy, a sweep, or the copy out.
+enum Phase { kCopyIn = 0, kSweep = 1, kCopyOut = 2 };
+
 struct Job {
     ss_job_info info{};
     ss_plan_t plan = nullptr;
@@ -57,7 +62,11 @@ struct Job {
     size_t grid_bytes = 0;
     size_t arena_off = 0;
     char *buf[2] = {nullptr, nullptr};
-    int cur = 0;  // buffer holding the current state
+    int cur = 0;                 // buffer holding the current state
+    hipEvent_t done = nullptr;   // completes the job's work in flight
+    bool busy = false;           // work in flight
+    Phase phase = kCopyIn;
+    int advance = 0;             // sweeps the launch in flight applies
 };
 
 }  // namespace
@@ -69,10 +78,11 @@ struct ss_server_ {
     int max_jobs = 0;
     int device = 0;
     std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> event_pool;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Job *> queue;       // submitted, not admitted (FIFO)
-    std::vector<Job *> running;    // admitted, stepping
+    std::vector<Job *> running;    // admitted (worker thread only)
     std::unordered_map<uint64_t, Job *> jobs;
     uint64_t next_id = 1;
     int live = 0;                  // queued + running
@@ -85,95 +95,171 @@ struct ss_server_ {
     double now() const {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
+    hipEvent_t take_event() {
+        if (!event_pool.empty()) {
+            hipEvent_t e = event_pool.back();
+            event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        return e;
+    }
+    // the stream of a plan class (a class's launches stay in order)
+    hipStream_t stream_of(const ss_plan_ *p) const { return streams[p->klass % streams.size()]; }
     void run();
+    bool step();
+    void fail(Job *j, ss_status st) {
+        j->info.status = st;
+        j->busy = false;
+    }
 };
+
+// One pass of the worker: retire finished device work, admit queued jobs,
+// launch the next sweep of every idle class group.  Returns whether
+// anything happened.
+bool ss_server_::step() {
+    // the records are read by poll() and the queue is fed by submit(): hold
+    // the lock for the pass (the device calls below only enqueue work)
+    std::lock_guard<std::mutex> lk(mu);
+    bool progress = false;
+    std::vector<Job *> finished;
+    // 1. device work that completed
+    for (Job *j : running) {
+        if (!j->busy) continue;
+        const hipError_t q = hipEventQuery(j->done);
+        if (q == hipErrorNotReady) continue;
+        progress = true;
+        j->busy = false;
+        if (q != hipSuccess) {
+            fail(j, SS_E_DEVICE);
+            finished.push_back(j);
+            continue;
+        }
+        if (j->phase == kSweep) {
+            j->cur ^= 1;
+            j->info.steps_done += j->advance;
+        } else if (j->phase == kCopyOut) {
+            finished.push_back(j);
+        }
+    }
+    // 2. jobs whose sweeps are done (or failed) copy their result out
+    for (Job *j : running) {
+        if (j->busy || j->phase == kCopyOut) continue;
+        if (j->info.status != SS_OK) {
+            if (std::find(finished.begin(), finished.end(), j) == finished.end()) finished.push_back(j);
+            continue;
+        }
+        if (j->info.steps_done < j->info.steps_total) continue;
+        hipStream_t st = stream_of(j->plan);
+        if (hipMemcpyAsync(j->out, j->buf[j->cur], j->grid_bytes, hipMemcpyDefault, st) != hipSuccess ||
+            hipEventRecord(j->done, st) != hipSuccess) {
+            fail(j, SS_E_DEVICE);
+            finished.push_back(j);
+            continue;
+        }
+        j->phase = kCopyOut;
+        j->busy = true;
+        progress = true;
+    }
+    // 3. retire: free arena space and publish the record
+    if (!finished.empty()) {
+        const double t = now();
+        for (Job *j : finished) {
+            j->info.state = j->info.status == SS_OK ? 2 : 3;
+            j->info.t_done = t;
+            arena.release(j->arena_off);
+            event_pool.push_back(j->done);
+            j->done = nullptr;
+            running.erase(std::find(running.begin(), running.end(), j));
+            --live;
+        }
+        cv.notify_all();
+    }
+    // 4. admission, FIFO while the arena has room for both buffers
+    {
+        while (!queue.empty()) {
+            Job *j = queue.front();
+            size_t off;
+            if (!arena.alloc(2 * round_up(j->grid_bytes), &off)) break;
+            hipEvent_t e = take_event();
+            if (!e) {
+                arena.release(off);
+                break;
+            }
+            queue.pop_front();
+            j->arena_off = off;
+            j->buf[0] = arena_base + off;
+            j->buf[1] = arena_base + off + round_up(j->grid_bytes);
+            j->cur = 0;
+            j->done = e;
+            j->info.state = 1;
+            j->info.t_admit = now();
+            running.push_back(j);
+            hipStream_t st = stream_of(j->plan);
+            if (hipMemcpyAsync(j->buf[0], j->in, j->grid_bytes, hipMemcpyDefault, st) != hipSuccess ||
+                hipEventRecord(j->done, st) != hipSuccess) {
+                j->info.status = SS_E_DEVICE;
+            } else {
+                j->phase = kCopyIn;
+                j->busy = true;
+            }
+            progress = true;
+        }
+    }
+    // 5. next sweep of every idle job, grouped by plan class (fused sweeps
+    // and leftover single sweeps are different classes)
+    std::vector<std::pair<const ss_plan_ *, std::vector<Job *>>> groups;
+    for (Job *j : running) {
+        if (j->busy || j->info.status != SS_OK || j->info.steps_done >= j->info.steps_total) continue;
+        const int64_t left = j->info.steps_total - j->info.steps_done;
+        const ss_plan_ *sub = (j->plan->fuse > 1 && left < j->plan->fuse) ? j->plan->rem : j->plan;
+        auto g = std::find_if(groups.begin(), groups.end(), [&](const auto &e) {
+            return e.second.size() < (size_t)ss::kMaxJobs && ss::same_class(e.first, sub);
+        });
+        if (g == groups.end()) groups.push_back({sub, {j}});
+        else g->second.push_back(j);
+    }
+    for (auto &grp : groups) {
+        const void *in[ss::kMaxJobs];
+        void *out[ss::kMaxJobs];
+        int64_t dims[ss::kMaxJobs][3];
+        for (size_t t = 0; t < grp.second.size(); ++t) {
+            Job *j = grp.second[t];
+            in[t] = j->buf[j->cur];
+            out[t] = j->buf[j->cur ^ 1];
+            std::memcpy(dims[t], j->plan->dims, sizeof dims[t]);
+        }
+        hipStream_t st = stream_of(grp.first);
+        bool ok = ss::sweep_grids(grp.first, (int)grp.second.size(), in, out, dims, st) == hipSuccess;
+        // every job of the launch records its own event after it
+        for (Job *j : grp.second) ok = ok && hipEventRecord(j->done, st) == hipSuccess;
+        for (Job *j : grp.second) {
+            if (!ok) {
+                fail(j, SS_E_DEVICE);
+                continue;
+            }
+            j->phase = kSweep;
+            j->advance = grp.first == j->plan ? j->plan->fuse : 1;
+            j->busy = true;
+        }
+        progress = true;
+    }
+    return progress;
+}
 
 void ss_server_::run() {
     (void)hipSetDevice(device);
     for (;;) {
-        std::vector<Job *> active;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv.wait(lk, [&] { return stop || !queue.empty() || !running.empty(); });
-            if (stop && queue.empty() && running.empty()) return;
-            // admission: FIFO while the arena has room for both buffers
-            while (!queue.empty()) {
-                Job *j = queue.front();
-                size_t off;
-                if (!arena.alloc(2 * round_up(j->grid_bytes), &off)) break;
-                queue.pop_front();
-                j->arena_off = off;
-                j->buf[0] = arena_base + off;
-                j->buf[1] = arena_base + off + round_up(j->grid_bytes);
-                j->cur = 0;
-                j->info.state = 1;
-                j->info.t_admit = now();
-                running.push_back(j);
-                if (hipMemcpyAsync(j->buf[0], j->in, j->grid_bytes, hipMemcpyDefault, streams[0]) !=
-                    hipSuccess)
-                    j->info.status = SS_E_DEVICE;
-            }
-            active = running;
+            if (stop && queue.empty() && running.empty()) break;
         }
-        (void)hipStreamSynchronize(streams[0]);  // admission copies landed
-        // one round: every running job advances by one (fused) sweep
-        std::vector<std::pair<const ss_plan_ *, std::vector<Job *>>> groups;
-        std::unordered_map<Job *, int> advance;
-        for (Job *j : active) {
-            const int64_t left = j->info.steps_total - j->info.steps_done;
-            const ss_plan_ *sub = (j->plan->fuse > 1 && left < j->plan->fuse) ? j->plan->rem : j->plan;
-            advance[j] = sub == j->plan ? j->plan->fuse : 1;
-            auto g = std::find_if(groups.begin(), groups.end(), [&](const auto &e) {
-                return e.second.size() < (size_t)ss::kMaxJobs && ss::same_class(e.first, sub);
-            });
-            if (g == groups.end()) groups.push_back({sub, {j}});
-            else g->second.push_back(j);
-        }
-        std::vector<bool> used(streams.size(), false);
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            auto &grp = groups[gi];
-            const void *in[ss::kMaxJobs];
-            void *out[ss::kMaxJobs];
-            int64_t dims[ss::kMaxJobs][3];
-            for (size_t t = 0; t < grp.second.size(); ++t) {
-                Job *j = grp.second[t];
-                in[t] = j->buf[j->cur];
-                out[t] = j->buf[j->cur ^ 1];
-                std::memcpy(dims[t], j->plan->dims, sizeof dims[t]);
-            }
-            const size_t si = gi % streams.size();
-            used[si] = true;
-            if (ss::sweep_grids(grp.first, (int)grp.second.size(), in, out, dims, streams[si]) != hipSuccess)
-                for (Job *j : grp.second) j->info.status = SS_E_DEVICE;
-        }
-        for (size_t si = 0; si < streams.size(); ++si)
-            if (used[si]) (void)hipStreamSynchronize(streams[si]);
-        // retire finished jobs, free their memory
-        std::vector<Job *> finished;
-        for (Job *j : active) {
-            j->cur ^= 1;
-            j->info.steps_done += advance[j];
-            if (j->info.steps_done >= j->info.steps_total || j->info.status != SS_OK) finished.push_back(j);
-        }
-        for (Job *j : finished)
-            if (j->info.status == SS_OK &&
-                hipMemcpyAsync(j->out, j->buf[j->cur], j->grid_bytes, hipMemcpyDefault, streams[0]) !=
-                    hipSuccess)
-                j->info.status = SS_E_DEVICE;
-        if (!finished.empty()) (void)hipStreamSynchronize(streams[0]);
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            const double t = now();
-            for (Job *j : finished) {
-                j->info.state = j->info.status == SS_OK ? 2 : 3;
-                j->info.t_done = t;
-                arena.release(j->arena_off);
-                running.erase(std::find(running.begin(), running.end(), j));
-                --live;
-            }
-        }
-        if (!finished.empty()) cv.notify_all();
+        if (!step()) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
+    for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    event_pool.clear();
 }
 
 extern "C" {
