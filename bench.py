@@ -26,7 +26,9 @@ SWEEPS = 100
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = 8  # FP32 state: one 4-byte read and one 4-byte write per point-sweep
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smfmac_box2d9p_10240.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_22969_amd", "csrc", "mma2d.hip")
+# sources of the sparse 2-D sweep kernel the traffic figure was measured on
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2506_22969_amd", "csrc", f)
+               for f in ("mma2d_impl.hpp", "mma2d_f32.hip", "kgeom.hpp", "kargs.hpp")]
 
 
 def parse():
@@ -51,8 +53,11 @@ def parse():
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_entry():
