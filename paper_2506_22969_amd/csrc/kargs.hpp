@@ -34,8 +34,9 @@ struct MmaArgs {
     const uint4 *a_hi;       // [MB][KC][64] A fragments (8 x 16-bit each)
     const uint4 *a_lo;
     const uint32_t *a_idx;   // [MB][KC][64] sparse index words (sparse mode)
-    const int32_t *boff;     // [KC][4][VPK] gather offsets in state elements
+    const int32_t *boff;     // [KC][4][VPK] gather offsets in bytes
     const void *zeros;       // 1 KiB of zeros (loads outside a zero-halo grid)
+    const float *w;          // (2r+1)^2 coefficients (direct LDS kernel only)
 };
 
 struct DirectJob {
@@ -78,6 +79,10 @@ enum DirectKind { kDirectF32 = 0, kDirectF64 = 1, kDirectPlanes = 2 };
 MmaLaunch find_mma3d(const MmaKey &key);
 bool mma3d_geometry(const MmaKey &key, int *wgh, int *row);
 int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max);
+
+// Direct 2-D sweep from the same LDS-DMA slab pipeline (FP32 state or
+// bfloat16 planes); nullptr when no kernel exists for the radius.
+MmaLaunch find_lds_direct2d(int rad, int state);
 
 // Dense FP64 MMA sweep (tile 8 x 4, FP64 state and coefficients): the
 // launch for radius `rad` and KC chunks of 4, and its slab row pitch.

@@ -435,12 +435,20 @@ ss_status plan_mma2d_f64(ss_plan_ *p) {
 
 ss_status plan_direct(ss_plan_ *p) {
     const bool f64 = p->dtype == SS_F64;
-    std::vector<uint8_t> blob(p->w.size() * (f64 ? 8 : 4));
+    // 2-D FP32-state or plane grids run on the LDS-pipelined kernel (planes
+    // need rows of a multiple of 8 values); FP64, 1-D and 3-D on the plain one
+    const int state = mma_state(p->dtype);
+    MmaLaunch lds = nullptr;
+    if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0))
+        lds = find_lds_direct2d(p->rad, state);
+    const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
+    const size_t o_zero = (wbytes + 255) & ~(size_t)255;
+    std::vector<uint8_t> blob(o_zero + 1024, 0);
     if (f64) {
-        std::memcpy(blob.data(), p->w.data(), blob.size());
+        std::memcpy(blob.data(), p->w.data(), wbytes);
     } else {
         std::vector<float> wf(p->w.begin(), p->w.end());
-        std::memcpy(blob.data(), wf.data(), blob.size());
+        std::memcpy(blob.data(), wf.data(), wbytes);
     }
     ss_status st = upload(p, blob);
     if (st != SS_OK) return st;
@@ -449,6 +457,14 @@ ss_status plan_direct(ss_plan_ *p) {
     p->dargs.rx = p->rad;
     p->dargs.periodic = p->boundary == SS_BC_PERIODIC;
     p->dargs.w = p->dev;
+    if (lds) {
+        char *d = static_cast<char *>(p->dev);
+        p->mma = lds;
+        p->margs.periodic = p->boundary == SS_BC_PERIODIC;
+        p->margs.w = reinterpret_cast<const float *>(d);
+        p->margs.zeros = d + o_zero;
+        p->margs.inv_sigma = 1.0f;
+    }
     p->engine = SS_ENGINE_DIRECT;
     p->info.passes = 1;
     p->info.sigma = 1.0;
@@ -606,7 +622,7 @@ namespace ss {
 hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
                        const int64_t (*dims)[3], hipStream_t s) {
     if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
-    if (p->engine == SS_ENGINE_DIRECT) {
+    if (!p->mma) {
         DirectArgs a = p->dargs;
         a.njobs = n;
         for (int j = 0; j < n; ++j)
