@@ -79,6 +79,8 @@ struct MmaGeom {
 // WGH rows) over a range of z planes; the workgroup marches through z with a
 // ring of NP plane slabs in LDS, each output plane using the 2*RAD+1 input
 // planes around it.  Each wave multiplies one unit (16 tiles) per plane.
+// A slab row holds the band's 256 values at HL and four halo values on each
+// side (whole 16-byte transfers), so RAD is at most 4.
 template <int R1, int R2, int RAD>
 struct Mma3Geom {
     static constexpr int MB = R1 * R2 / 16;
@@ -87,14 +89,11 @@ struct Mma3Geom {
     static constexpr int NBH = NBY * R2;
     static constexpr int WGH = kWaves / kNbCols * NBH;  // rows of a work item
     static constexpr int SROWS = WGH + 2 * RAD;
-    static constexpr int HL = (RAD + 3) / 4 * 4;
+    static constexpr int HL = 4;
     static constexpr int CPITCH = (HL + kBandX + RAD + 3) / 4 * 4 + 4;
     static constexpr int PLANE_BYTES = SROWS * CPITCH * 4;
-    static constexpr int NHALO = SROWS * 2 * RAD;       // halo dwords per plane (moved by wave 0)
-    static constexpr int HOPS = (NHALO + 63) / 64;
-    static constexpr int HSTRIP = HOPS * 64;
-    static constexpr int SLOT = PLANE_BYTES + 4 * HSTRIP;
-    static constexpr int NP = kLdsBytes / SLOT < 8 ? kLdsBytes / SLOT : 8;  // ring slots
+    static constexpr int NP = kLdsBytes / PLANE_BYTES < 8 ? kLdsBytes / PLANE_BYTES : 8;  // ring slots
+    static_assert(RAD <= 4 && CPITCH >= HL + kBandX + 4, "slab row holds four halo values a side");
     static_assert(NP >= 2 * RAD + 2, "ring too small for the stencil depth");
 };
 

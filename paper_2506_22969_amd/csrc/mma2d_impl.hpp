@@ -42,26 +42,33 @@ typedef __bf16 bh16 __attribute__((ext_vector_type(16)));
 typedef unsigned u8v __attribute__((ext_vector_type(8)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v __attribute__((ext_vector_type(2)));
 
-// Split two FP32 values into packed hi parts and sigma-scaled lo parts.
+// Split two FP32 values into packed hi parts and sigma-scaled lo parts,
+// rounding to nearest even.  x - hi is exact in FP32.  binary16: one packed
+// conversion for the hi pair, x - hi by mixed-precision FMAs that read the
+// binary16 halves directly, and (x - hi) * sigma rounded into the lo and hi
+// halves of the lo word.  bfloat16: packed conversions both ways.
 template <int PART>
 __device__ inline void split2(float x0, float x1, float sigma, unsigned *hi, unsigned *lo) {
+    const f2v x = {x0, x1};
     if constexpr (PART == kPartF16) {
-        const _Float16 h0 = (_Float16)x0, h1 = (_Float16)x1;
-        const _Float16 l0 = (_Float16)((x0 - (float)h0) * sigma);
-        const _Float16 l1 = (_Float16)((x1 - (float)h1) * sigma);
-        *hi = (unsigned)__builtin_bit_cast(unsigned short, h0) |
-              ((unsigned)__builtin_bit_cast(unsigned short, h1) << 16);
-        *lo = (unsigned)__builtin_bit_cast(unsigned short, l0) |
-              ((unsigned)__builtin_bit_cast(unsigned short, l1) << 16);
+        const unsigned h = __builtin_bit_cast(unsigned, __builtin_convertvector(x, h2v));
+        float d0, d1;
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(d0) : "v"(h), "v"(x0));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(d1) : "v"(h), "v"(x1));
+        unsigned l;
+        asm("v_fma_mixlo_f16 %0, %1, %2, 0" : "=v"(l) : "v"(d0), "v"(sigma));
+        asm("v_fma_mixhi_f16 %0, %1, %2, 0" : "+v"(l) : "v"(d1), "v"(sigma));
+        *hi = h;
+        *lo = l;
     } else {
-        const __bf16 h0 = (__bf16)x0, h1 = (__bf16)x1;
-        const __bf16 l0 = (__bf16)((x0 - (float)h0) * sigma);
-        const __bf16 l1 = (__bf16)((x1 - (float)h1) * sigma);
-        *hi = (unsigned)__builtin_bit_cast(unsigned short, h0) |
-              ((unsigned)__builtin_bit_cast(unsigned short, h1) << 16);
-        *lo = (unsigned)__builtin_bit_cast(unsigned short, l0) |
-              ((unsigned)__builtin_bit_cast(unsigned short, l1) << 16);
+        const b2v h = __builtin_convertvector(x, b2v);
+        const f2v r = (x - __builtin_convertvector(h, f2v)) * sigma;
+        *hi = __builtin_bit_cast(unsigned, h);
+        *lo = __builtin_bit_cast(unsigned, __builtin_convertvector(r, b2v));
     }
 }
 

@@ -14,6 +14,8 @@
 // those is complete after the plane and is stored.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "mma2d_impl.hpp"
 
 namespace ss {
@@ -22,92 +24,90 @@ template <int R1, int R2, int RAD, bool VEC>
 struct Pipe3 {
     using G = Mma3Geom<R1, R2, RAD>;
     static constexpr int DRW = (G::SROWS + kWaves - 1) / kWaves;   // rows each wave loads per plane
-    static constexpr int DMA_PER_ROW = VEC ? 1 : kBandX / 64;
-    static constexpr int D1 = DRW * DMA_PER_ROW;                   // VMEM loads per plane, waves 1..7
-    static constexpr int D0 = D1 + G::HOPS;                        // ... wave 0 (also the halo)
-    static constexpr int M = G::MB * (VEC ? 1 : 4);                // VMEM stores per output plane
+    // a row is 264 values from HL-4: 64 lanes x 16 bytes and 2 lanes x 16
+    // bytes, or 4 x 64 lanes x 4 bytes and 8 lanes x 4 bytes
+    static constexpr int DMA_PER_ROW = VEC ? 2 : 5;
+    static constexpr int D = DRW * DMA_PER_ROW;                    // VMEM loads per wave per plane
+    static constexpr int M = G::MB * (VEC ? 1 : 4);                // VMEM stores per wave per output plane
     static constexpr int A = 2 * RAD;                              // steps before the first store
-    // VMEM operations issued after load p when step p consumes it: loads
-    // 0..NP-2 are issued before step 0, step j issues load j+NP-1 and then,
-    // from step A on, the stores of one output plane; S = min(max(p-A, 0),
-    // NP-1) counts the steps with stores among those that follow load p
-    template <int D, int S>
-    static constexpr int W = (G::NP - 2) * D + S * M;
+    // Step l waits for plane l + 1 (its B operands are gathered while the
+    // matrix cores multiply plane l).  VMEM operations a wave has issued
+    // after the loads of plane l + 1 at that point: the loads of the NP-3
+    // planes issued after it and at most the stores of the NP-2 steps since.
+    // From step A + NP - 2 on that is exact (WS); before it fewer stores
+    // follow, and waiting for WL (no stores) waits for a few more loads than
+    // needed.  Plane 0 is waited for before the first step (W0).
+    static constexpr int W0 = (G::NP - 2) * D;
+    static constexpr int WL = (G::NP - 3) * D;
+    static constexpr int WS = (G::NP - 3) * D + (G::NP - 2) * M;
+    static constexpr int STEADY = A + G::NP - 2;
 };
 
-template <int D, int R1, int R2, int RAD, bool VEC>
-__device__ inline void wait_step3(int p) {
-    using P = Pipe3<R1, R2, RAD, VEC>;
-    constexpr int NP = Mma3Geom<R1, R2, RAD>::NP;
-    const int st = min(max(p - P::A, 0), NP - 1);
-    static_assert(NP <= 8, "wait table covers up to 8 ring slots");
-    switch (st) {
-        case 0: wait_vmcnt<P::template W<D, 0>>(); break;
-        case 1: wait_vmcnt<P::template W<D, 1>>(); break;
-        case 2: wait_vmcnt<P::template W<D, 2>>(); break;
-        case 3: wait_vmcnt<P::template W<D, 3>>(); break;
-        case 4: wait_vmcnt<P::template W<D, 4>>(); break;
-        case 5: wait_vmcnt<P::template W<D, 5>>(); break;
-        case 6: wait_vmcnt<P::template W<D, 6>>(); break;
-        default: wait_vmcnt<P::template W<D, 7>>(); break;
-    }
-}
-
-// Issue the transfers of input plane z (already wrapped, or outside the grid
-// with a zero halo) into a ring slot: every row of the slab by every wave
-// (rows clamped, so all waves issue DRW rows), halo columns by wave 0.
+// Issue the transfers of input plane z (already wrapped; outside the grid
+// with a zero halo) into a ring slot.  Every wave moves the slab rows wave,
+// wave + 8, ... (clamped to the last row, so that all waves issue the same
+// count); rows are item constants, passed as element offsets (-1: outside
+// the grid) with the slab row addresses.
 template <int R1, int R2, int RAD, bool VEC, int BC>
-__device__ inline void issue_plane(const MmaArgs &p, const MmaJob &g, char *slab, unsigned *strip, int X0,
-                                   int Y0, int z) {
-    using G = Mma3Geom<R1, R2, RAD>;
+__device__ inline void issue_plane(const MmaJob &g, const float *zf, unsigned slot_lds,
+                                   const int (&row_off)[Pipe3<R1, R2, RAD, VEC>::DRW],
+                                   const unsigned (&row_lds)[Pipe3<R1, R2, RAD, VEC>::DRW], int X0, int z) {
     using P = Pipe3<R1, R2, RAD, VEC>;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    X0 = __builtin_amdgcn_readfirstlane(X0);
-    Y0 = __builtin_amdgcn_readfirstlane(Y0);
-    z = __builtin_amdgcn_readfirstlane(z);
     const bool z_ok = BC != kBcZero || (z >= 0 && z < g.nz);
     const float *in = static_cast<const float *>(g.in) + (size_t)(z_ok ? z : 0) * g.ny * g.nx;
-    const float *zf = static_cast<const float *>(p.zeros);
+    if constexpr (VEC) {
+        // chunk c of the row holds columns X0 - 4 + 4c (c = 0..65)
+        const int gxa = wrap<BC>(X0 - 4 + 4 * lane, g.nx);
+        const int gxb = wrap<BC>(X0 + 252 + 4 * lane, g.nx);
+        const bool oka = BC != kBcZero || (gxa >= 0 && gxa < g.nx);
+        const bool okb = BC != kBcZero || (gxb >= 0 && gxb < g.nx);
 #pragma unroll
-    for (int d = 0; d < P::DRW; ++d) {
-        const int r = min(wave + d * kWaves, G::SROWS - 1);
-        const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
-        const bool row_ok = BC != kBcZero || (z_ok && gy >= 0 && gy < g.ny);
-        const unsigned dst = lds_addr_of(reinterpret_cast<float *>(slab) + r * G::CPITCH + G::HL);
-        if constexpr (VEC) {
-            const int gx = wrap<BC>(X0 + 4 * lane, g.nx);
-            const bool ok = BC != kBcZero || (row_ok && gx < g.nx);
-            lds_dma16(ok ? in + (size_t)gy * g.nx + gx : zf + 4 * lane, dst);
-        } else {
+        for (int d = 0; d < P::DRW; ++d) {
+            const bool row_ok = z_ok && row_off[d] >= 0;
+            const float *row = in + row_off[d];
+            lds_dma16(row_ok && oka ? row + gxa : zf, slot_lds + row_lds[d]);
+            if (lane < 2) lds_dma16(row_ok && okb ? row + gxb : zf, slot_lds + row_lds[d] + 1024);
+        }
+    } else {
 #pragma unroll
-            for (int h = 0; h < P::DMA_PER_ROW; ++h) {
-                const int gx = wrap<BC>(X0 + 64 * h + lane, g.nx);
-                const bool ok = BC != kBcZero || (row_ok && gx < g.nx);
-                lds_dma4(ok ? in + (size_t)gy * g.nx + gx : zf + lane, dst + 256 * h);
+        for (int d = 0; d < P::DRW; ++d) {
+            const bool row_ok = z_ok && row_off[d] >= 0;
+            const float *row = in + row_off[d];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int gx = wrap<BC>(X0 - 4 + 64 * h + lane, g.nx);
+                const bool ok = BC != kBcZero || (gx >= 0 && gx < g.nx);
+                lds_dma4(row_ok && ok ? row + gx : zf, slot_lds + row_lds[d] + 256 * h);
+            }
+            if (lane < 8) {
+                const int gx = wrap<BC>(X0 + 252 + lane, g.nx);
+                const bool ok = BC != kBcZero || (gx >= 0 && gx < g.nx);
+                lds_dma4(row_ok && ok ? row + gx : zf, slot_lds + row_lds[d] + 1024);
             }
         }
     }
-    if (wave == 0) {
-#pragma unroll
-        for (int h = 0; h < G::HOPS; ++h) {
-            const int e = min(h * 64 + lane, G::NHALO - 1);
-            const int r = e / (2 * RAD), j = e % (2 * RAD);
-            const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
-            const int gx = wrap<BC>(j < RAD ? X0 - RAD + j : X0 + kBandX + (j - RAD), g.nx);
-            const bool ok = BC != kBcZero || (z_ok && gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx);
-            lds_dma4(ok ? in + (size_t)gy * g.nx + gx : zf + lane, lds_addr_of(strip + h * 64));
-        }
-    }
 }
 
-template <int R1, int R2, int RAD>
-__device__ inline void put_halo3(char *slab, const unsigned *strip) {
-    using G = Mma3Geom<R1, R2, RAD>;
-    for (int e = threadIdx.x; e < G::NHALO; e += kThreads) {
-        const int r = e / (2 * RAD), j = e % (2 * RAD);
-        const int c = j < RAD ? G::HL - RAD + j : G::HL + kBandX + (j - RAD);
-        reinterpret_cast<unsigned *>(slab)[r * G::CPITCH + c] = strip[e];
+// Gather offset of B register v with the word passed through an empty asm
+// that takes the plane index: the unpacking stays inside the plane loop (it
+// is not hoisted and kept live), and since the asm touches no memory the LDS
+// reads of a plane can be issued together.
+template <int VPK>
+__device__ inline int plane_off(const unsigned (&o2)[VPK / 2], int v, int l) {
+    unsigned w = o2[v >> 1];
+    asm("" : "+v"(w) : "s"(l));
+    return (v & 1) ? (int)(w >> 16) : (int)(w & 0xffffu);
+}
+
+// Calls f(integral_constant<R>, l0 + R) for R = 0..N-1 while l0 + R < n.
+template <int R, int N, typename F>
+__device__ inline void unroll_steps(F &f, int l0, int n) {
+    if constexpr (R < N) {
+        if (l0 + R < n) {
+            f(std::integral_constant<int, R>{}, l0 + R);
+            unroll_steps<R + 1, N>(f, l0, n);
+        }
     }
 }
 
@@ -121,11 +121,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     constexpr int NZ = 2 * RAD + 1;          // plane offsets of the stencil
     constexpr int CPP = KC / NZ;             // K chunks per input plane
     static_assert(CPP * NZ == KC, "chunks must not straddle planes");
-    __shared__ __attribute__((aligned(16))) char lds[NP * G::SLOT];
-    auto slab = [&](int i) { return lds + i * G::PLANE_BYTES; };
-    auto strip = [&](int i) { return reinterpret_cast<unsigned *>(lds + NP * G::PLANE_BYTES) + i * G::HSTRIP; };
+    __shared__ __attribute__((aligned(16))) char lds[NP * G::PLANE_BYTES];
+    const unsigned lds0 = lds_addr_of(lds);
 
     const float sigma = 1.0f / p.inv_sigma;
+    const float inv_sigma = p.inv_sigma;
+    const float *zf = static_cast<const float *>(p.zeros);
     // XCD-aware contiguous item ranges, as in the 2-D kernel
     const int nxcd = p.nxcd;
     const int nwg = gridDim.x;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     const int first = range_begin + blockIdx.x / nxcd;
 
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q = lane >> 4;
     // every plane has the same K order (shifted by whole planes), so the
     // gather offsets of its CPP chunks serve all plane offsets
@@ -165,31 +166,46 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     const int tx_t = n % G::NBX, ty_t = n / G::NBX;
     const int nbc = wave % kNbCols, nb = wave / kNbCols;
     const int srow0 = nb * G::NBH + ty_t * R2;  // tile's first output row in the item
+    // slab rows this wave moves (LDS byte offset within a slot)
+    unsigned row_lds[P::DRW];
+#pragma unroll
+    for (int d = 0; d < P::DRW; ++d) row_lds[d] = min(wave + d * kWaves, G::SROWS - 1) * G::CPITCH * 4;
+    // byte offset of the tile's patch origin within a slot
+    const int tbo = (srow0 * G::CPITCH + (G::HL - RAD) + nbc * 128 + tx_t * R1) * 4;
 
 #pragma unroll 1
     for (int it = first; it < range_end; it += stride) {
         // item -> job, band, row block, z chunk
         int j = 0;
         for (int t = 1; t < p.njobs; ++t) j += it >= p.job[t].item0 ? 1 : 0;
-        const MmaJob &g = p.job[j];
+        // a copy in registers: the transfers' memory clobbers would
+        // otherwise make every use reload the job from the argument block
+        const MmaJob g = p.job[j];
         const int nbands = (g.nx + kBandX - 1) / kBandX, nrb = (g.ny + G::WGH - 1) / G::WGH;
         int local = it - g.item0;
-        const int X0 = (local % nbands) * kBandX;
+        const int X0 = __builtin_amdgcn_readfirstlane((local % nbands) * kBandX);
         local /= nbands;
-        const int Y0 = (local % nrb) * G::WGH;
-        const int z0 = (local / nrb) * g.zc;
+        const int Y0 = __builtin_amdgcn_readfirstlane((local % nrb) * G::WGH);
+        const int z0 = __builtin_amdgcn_readfirstlane((local / nrb) * g.zc);
         const int nzc = min(g.zc, g.nz - z0);
         const int nload = nzc + 2 * RAD;   // input planes z0-RAD .. z0+nzc-1+RAD
+        // element offsets of this wave's slab rows within a plane (-1 outside)
+        int row_off[P::DRW];
+#pragma unroll
+        for (int d = 0; d < P::DRW; ++d) {
+            const int gy = wrap<BC>(Y0 - RAD + min(wave + d * kWaves, G::SROWS - 1), g.ny);
+            row_off[d] = (BC != kBcZero || (gy >= 0 && gy < g.ny)) ? gy * g.nx : -1;
+        }
         auto issue = [&](int l) {
             const int zz = wrap<BC>(z0 - RAD + min(l, nload - 1), g.nz);
-            issue_plane<R1, R2, RAD, VEC, BC>(p, g, slab(l % NP), strip(l % NP), X0, Y0, zz);
+            issue_plane<R1, R2, RAD, VEC, BC>(g, zf, lds0 + (l % NP) * G::PLANE_BYTES, row_off, row_lds, X0, zz);
         };
 #pragma unroll 1
         for (int l = 0; l < NP - 1; ++l) issue(l);
         const int rows_left = min(G::WGH, g.ny - Y0);
         const int xbase = X0 + nbc * 128 + tx_t * R1;
-        // acc[i] accumulates output plane z0 + (l - 2*RAD + i) at step l
-        // hi*hi, hi*lo and lo*hi accumulate separately
+        // output plane z0 + l - 2*RAD + i accumulates at step l in slot
+        // (i + l) % NZ; hi*hi, hi*lo and lo*hi accumulate separately
         f4 accm[NZ][MB], acc1[NZ][MB], acc2[NZ][MB];
 #pragma unroll
         for (int i = 0; i < NZ; ++i)
@@ -199,37 +215,53 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                 acc1[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
                 acc2[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
-#pragma unroll 1
-        for (int l = 0; l < nload; ++l) {
-            if (wave == 0) wait_step3<P::D0, R1, R2, RAD, VEC>(l);
-            else wait_step3<P::D1, R1, R2, RAD, VEC>(l);
-            __builtin_amdgcn_s_barrier();
-            put_halo3<R1, R2, RAD>(slab(l % NP), strip(l % NP));
-            __builtin_amdgcn_s_waitcnt(0xC07F);
-            __builtin_amdgcn_s_barrier();
-            issue(l + NP - 1);
-            // input plane l: once into B registers, times every plane offset
-            const char *tb =
-                slab(l % NP) + (srow0 * G::CPITCH + (G::HL - RAD) + nbc * 128 + tx_t * R1) * 4;
+        // B operands of two planes: the one multiplied and the next one
+        unsigned bh[2][CPP][VPK], bl[2][CPP][VPK];
+        auto gather = [&](auto buf, int l) {
+            constexpr int PB = decltype(buf)::value;
+            const char *tb = lds + (l % NP) * G::PLANE_BYTES + tbo;
 #pragma unroll
             for (int c = 0; c < CPP; ++c) {
-                unsigned bh[VPK], bl[VPK];
+                float x[VPK][2];
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const float *src = reinterpret_cast<const float *>(tb + gather_off<VPK>(off2[c], v));
-                    split2<PART>(src[0], src[1], sigma, &bh[v], &bl[v]);
+                    const float *src = reinterpret_cast<const float *>(tb + plane_off<VPK>(off2[c], v, l));
+                    x[v][0] = src[0];
+                    x[v][1] = src[1];
                 }
+#pragma unroll
+                for (int v = 0; v < VPK; ++v) split2<PART>(x[v][0], x[v][1], sigma, &bh[PB][c][v], &bl[PB][c][v]);
+            }
+        };
+        wait_vmcnt<P::W0>();
+        __builtin_amdgcn_s_barrier();
+        gather(std::integral_constant<int, 0>{}, 0);
+        auto step = [&](auto phase, int l) {
+            constexpr int S = decltype(phase)::value;   // l % (2 * NZ)
+            constexpr int R = S % NZ, PB = S % 2;
+            if (l < P::STEADY) wait_vmcnt<P::WL>();
+            else wait_vmcnt<P::WS>();
+            // every wave's transfers of plane l + 1 have landed, and every
+            // wave is done with plane l - 1, whose slot the next issue
+            // refills
+            __builtin_amdgcn_s_barrier();
+            issue(l + NP - 1);
+            // plane l + 1 into B registers (past the last plane this reads
+            // the repeated last plane, unused) while plane l, gathered one
+            // step earlier, is multiplied by every plane offset
+            gather(std::integral_constant<int, 1 - PB>{}, l + 1);
+#pragma unroll
+            for (int c = 0; c < CPP; ++c)
 #pragma unroll
                 for (int pz = 0; pz < NZ; ++pz)
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
-                        const int kc = pz * CPP + c, i = NZ - 1 - pz;
-                        accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[i][mb], aidx[mb][kc]);
-                        acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl, acc1[i][mb], aidx[mb][kc]);
-                        acc2[i][mb] = mma<MODE, PART>(alo[mb][kc], bh, acc2[i][mb], aidx[mb][kc]);
+                        const int kc = pz * CPP + c, i = (NZ - 1 - pz + R) % NZ;
+                        accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh[PB][c], accm[i][mb], aidx[mb][kc]);
+                        acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl[PB][c], acc1[i][mb], aidx[mb][kc]);
+                        acc2[i][mb] = mma<MODE, PART>(alo[mb][kc], bh[PB][c], acc2[i][mb], aidx[mb][kc]);
                     }
-            }
-            // output plane z0 + l - 2*RAD is complete
+            // output plane z0 + l - 2*RAD (slot R) is complete
             if (l >= 2 * RAD) {
                 float *out = static_cast<float *>(g.out) + ((size_t)(z0 + l - 2 * RAD) * g.ny + Y0) * g.nx;
                 const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
@@ -240,7 +272,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                     const int gx = xbase + o % R1;
                     float ys[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ys[i] = accm[0][mb][i] + (acc1[0][mb][i] + acc2[0][mb][i]) * p.inv_sigma;
+                    for (int i = 0; i < 4; ++i) ys[i] = accm[R][mb][i] + (acc1[R][mb][i] + acc2[R][mb][i]) * inv_sigma;
                     const bool row_ok = gyr < rows_left;
                     if constexpr (VEC) {
                         const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
@@ -257,21 +289,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                     }
                 }
             }
-#pragma unroll
-            for (int i = 0; i + 1 < NZ; ++i)
-#pragma unroll
-                for (int mb = 0; mb < MB; ++mb) {
-                    accm[i][mb] = accm[i + 1][mb];
-                    acc1[i][mb] = acc1[i + 1][mb];
-                    acc2[i][mb] = acc2[i + 1][mb];
-                }
+            // slot R starts the newest output plane
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
-                accm[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                acc1[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                acc2[NZ - 1][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                accm[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc1[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
+                acc2[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
-        }
+        };
+#pragma unroll 1
+        for (int l0 = 0; l0 < nload; l0 += 2 * NZ) unroll_steps<0, 2 * NZ>(step, l0, nload);
         // the ring is refilled by the next item: let this item's transfers
         // (including the clamped ones past its last plane) land and every
         // wave finish reading first
