@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds2d(MmaArgs p) {
     auto issue = [&](int s) {
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
-        issue_item<8, 8, RAD, STATE, VEC, BC>(p, p.job[j], slab(s % NS), strip(s % NS), X0, Y0);
+        issue_item<8, 8, RAD, STATE, VEC, BC>(p.zeros, p.job[j], slab(s % NS), strip(s % NS), X0, Y0);
     };
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s) issue(s);

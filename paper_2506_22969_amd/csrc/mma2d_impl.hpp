@@ -191,7 +191,7 @@ __device__ inline unsigned lds_addr_of(const void *p) {
 // the same number of transfers for every item (item and row indices are
 // clamped), which is what the explicit waits count on.
 template <int R1, int R2, int RAD, int STATE, bool VEC, int BC>
-__device__ inline void issue_item(const MmaArgs &p, const MmaJob &g, char *slab, unsigned *strip, int X0,
+__device__ inline void issue_item(const void *zero_block, const MmaJob &g, char *slab, unsigned *strip, int X0,
                                   int Y0) {
     using G = MmaGeom<R1, R2, RAD, STATE>;
     using P = Pipe<R1, R2, RAD, STATE, VEC>;
@@ -199,7 +199,7 @@ __device__ inline void issue_item(const MmaArgs &p, const MmaJob &g, char *slab,
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     X0 = __builtin_amdgcn_readfirstlane(X0);
     Y0 = __builtin_amdgcn_readfirstlane(Y0);
-    const char *zeros = static_cast<const char *>(p.zeros);
+    const char *zeros = static_cast<const char *>(zero_block);
 #pragma unroll
     for (int d = 0; d < P::DRW; ++d) {
         const int r = min(wave + d * kWaves, G::SROWS - 1);
@@ -299,14 +299,14 @@ __device__ inline void put_halo(char *slab, const unsigned *strip) {
 }
 
 // Gather offset (bytes) of B register v of a K chunk: two 16-bit offsets
-// per word.
-// The empty asm hides the word's value from the optimiser, so that the
-// unpacked offsets are not hoisted out of the item loop and kept live (which
-// would undo the packing).
+// per word.  The word passes through an empty asm that takes a loop-varying
+// value (the item and unit number), so that the unpacked offsets are not hoisted out of
+// the loop and kept live (which would undo the packing); the asm touches no
+// memory, so the LDS reads around it can still be scheduled freely.
 template <int VPK>
-__device__ inline int gather_off(const unsigned (&o2)[VPK / 2], int v) {
+__device__ inline int gather_off(const unsigned (&o2)[VPK / 2], int v, int salt) {
     unsigned w = o2[v >> 1];
-    asm volatile("" : "+v"(w));
+    asm("" : "+v"(w) : "s"(salt));
     return (v & 1) ? (int)(w >> 16) : (int)(w & 0xffffu);
 }
 
@@ -314,11 +314,11 @@ __device__ inline int gather_off(const unsigned (&o2)[VPK / 2], int v) {
 // owns units (w / NCOLS) * U + u of unit column w % NCOLS: 16 tiles of
 // R2 x R1 outputs each.
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE, bool VEC>
-__device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const char *slab,
+__device__ inline void compute_item(float inv_sigma, const MmaJob &g, const char *slab,
                                     const uint4 (&ahi)[R1 * R2 / 16][KC], const uint4 (&alo)[R1 * R2 / 16][KC],
                                     const unsigned (&aidx)[R1 * R2 / 16][KC],
                                     const unsigned (&off2)[KC][(MODE == kSparse) ? 4 : 2], int X0, int Y0,
-                                    float sigma) {
+                                    float sigma, int salt) {
     using G = MmaGeom<R1, R2, RAD, STATE>;
     constexpr int MB = G::MB;
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
@@ -360,14 +360,14 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
                     if constexpr (G::PAIR_DWORD) {
-                        const unsigned *w = reinterpret_cast<const unsigned *>(tb + gather_off<VPK>(off2[kc], v));
+                        const unsigned *w = reinterpret_cast<const unsigned *>(tb + gather_off<VPK>(off2[kc], v, salt + u));
                         bh[v] = w[0];
                         bl[v] = w[G::LO / 2];
                     } else {
                         // the pair may start at an odd value: two dwords and
                         // a byte align (offset arithmetic stays relative to
                         // the slab, so the reads remain LDS reads)
-                        const int ai = tbo + gather_off<VPK>(off2[kc], v);
+                        const int ai = tbo + gather_off<VPK>(off2[kc], v, salt + u);
                         const unsigned *w = reinterpret_cast<const unsigned *>(slab + (ai & ~3));
                         const unsigned sh = (unsigned)(ai & 2);
                         bh[v] = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
@@ -377,7 +377,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
             } else {
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
-                    const float *src = reinterpret_cast<const float *>(tb + gather_off<VPK>(off2[kc], v));
+                    const float *src = reinterpret_cast<const float *>(tb + gather_off<VPK>(off2[kc], v, salt + u));
                     split2<PART>(src[0], src[1], sigma, &bh[v], &bl[v]);
                 }
             }
@@ -399,7 +399,7 @@ __device__ inline void compute_item(const MmaArgs &p, const MmaJob &g, const cha
             const int gx = xbase + o % R1;
             float ys[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ys[i] = accm[mb][i] + (acc1[mb][i] + acc2[mb][i]) * p.inv_sigma;
+            for (int i = 0; i < 4; ++i) ys[i] = accm[mb][i] + (acc1[mb][i] + acc2[mb][i]) * inv_sigma;
             const bool row_ok = gyr < rows_left;
             if constexpr (STATE == kStatePlanes) {
                 // bfloat16 hi = RNE(y), lo = RNE(y - hi); rows are a
@@ -464,6 +464,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
     auto strip = [&](int i) { return reinterpret_cast<unsigned *>(lds + NS * G::SLAB_BYTES) + i * G::HSTRIP; };
 
     const float sigma = 1.0f / p.inv_sigma;
+    const float inv_sigma = p.inv_sigma;
+    const void *zero_block = p.zeros;
     const int nxcd = p.nxcd;
     const int nwg = gridDim.x;
     const int xcd = blockIdx.x % nxcd;
@@ -514,7 +516,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
         const int i = s % NS;
-        issue_item<R1, R2, RAD, STATE, VEC, BC>(p, p.job[j], slab(i), strip(i), X0, Y0);
+        // a copy in registers: the transfers' memory clobbers would
+        // otherwise make every use reload the job from the argument block
+        const MmaJob g = p.job[j];
+        issue_item<R1, R2, RAD, STATE, VEC, BC>(zero_block, g, slab(i), strip(i), X0, Y0);
     };
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s) issue(s);
@@ -538,8 +543,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
         issue(s + NS - 1);
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
-        compute_item<R1, R2, KC, RAD, MODE, PART, STATE, VEC>(p, p.job[j], slab(cur), ahi, alo, aidx, off2,
-                                                               X0, Y0, sigma);
+        const MmaJob g = p.job[j];
+        compute_item<R1, R2, KC, RAD, MODE, PART, STATE, VEC>(inv_sigma, g, slab(cur), ahi, alo, aidx, off2, X0,
+                                                               Y0, sigma, s * G::U);
         if (first + (s + 1) * stride >= total) break;
     }
     // the pipeline always runs NS-1 items ahead: let those transfers land
