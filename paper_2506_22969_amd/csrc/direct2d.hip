@@ -59,7 +59,8 @@ __device__ inline void direct_item(const MmaJob &g, const float *wl, const char 
         for (int ry = 0; ry < kRowsPerThread + 2 * RAD; ++ry) {
             if constexpr (STATE == kStatePlanes) {
                 const unsigned short *s16 = reinterpret_cast<const unsigned short *>(slab);
-                v[ry] = bf16_value(s16[(y0 + ry) * G::PB + col]) + bf16_value(s16[G::LO + (y0 + ry) * G::PB + col]);
+                v[ry] = bf16_value(s16[planes_index<G::RBD>(y0 + ry, col, 0)]) +
+                        bf16_value(s16[planes_index<G::RBD>(y0 + ry, col, 1)]);
             } else {
                 v[ry] = reinterpret_cast<const float *>(slab)[(y0 + ry) * G::CPITCH + col];
             }
@@ -148,9 +149,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds2d(MmaArgs p) {
         }
         const int cur = s % NS;
         __builtin_amdgcn_s_barrier();
-        put_halo<8, 8, RAD, STATE>(slab(cur), strip(cur));
-        __builtin_amdgcn_s_waitcnt(0xC07F);
-        __builtin_amdgcn_s_barrier();
+        if constexpr (G::NHALO > 0) {
+            put_halo<8, 8, RAD, STATE>(slab(cur), strip(cur));
+            __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_s_barrier();
+        }
         issue(s + NS - 1);
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
@@ -182,7 +185,8 @@ hipError_t launch_lds2d(MmaArgs &a, hipStream_t s) {
         a.job[j].item0 = items;
         items += ((g.nx + kBandX - 1) / kBandX) * ((g.ny + G::WGH - 1) / G::WGH);
         vec = vec && (g.nx % (STATE == kStatePlanes ? 8 : 4)) == 0;
-        wrap1 = wrap1 && g.ny >= G::SROWS && g.nx >= kBandX + 2 * RAD + 2;
+        wrap1 = wrap1 && g.ny >= G::SROWS &&
+                g.nx >= kBandX + (STATE == kStatePlanes ? 2 * G::HLB : 2 * RAD + 2);
     }
     a.total_items = items;
     if (items == 0) return hipSuccess;

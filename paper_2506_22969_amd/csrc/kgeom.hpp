@@ -1,8 +1,9 @@
 // Geometry shared by the host runtime (table building, launch shapes) and the
 // 2-D MMA kernels.  A workgroup of 512 threads (8 waves of 64) owns a band 256
 // outputs wide and 32 rows tall (a work item).  A unit is the 16 tiles one MMA
-// covers along N (128 columns wide, NBH rows); the waves sit 2 across and 4
-// down the item and each multiplies U units stacked vertically.
+// covers along N (UW columns wide, NBH rows); the waves sit side by side
+// across the item (NCOLS unit columns) and down it, and each multiplies U
+// units stacked vertically.
 #pragma once
 
 namespace ss {
@@ -22,11 +23,11 @@ template <int R1, int R2, int RAD, int STATE>
 struct MmaGeom {
     static constexpr int MB = R1 * R2 / 16;            // 16-row M-blocks of A'
     // Tiles of a unit along x: a 128-column unit, except 16-wide tiles on
-    // the planes state, whose units are 4 tiles across and 4 tile rows down
+    // the planes state, whose units are 2 tiles across and 8 tile rows down
     // (with the row pitch below, the 16 tiles then start in 16 different
-    // LDS banks)
-    static constexpr bool SQUARE = STATE == kStatePlanes && R1 == 16;
-    static constexpr int NBX = SQUARE ? 4 : 128 / R1;
+    // pairs of LDS banks)
+    static constexpr bool TALL = STATE == kStatePlanes && R1 == 16;
+    static constexpr int NBX = TALL ? 2 : 128 / R1;
     static constexpr int NBY = 16 / NBX;               // ... along y
     static constexpr int NBH = NBY * R2;               // rows of a unit
     static constexpr int UW = NBX * R1;                // columns of a unit
@@ -40,33 +41,30 @@ struct MmaGeom {
     // halo columns, padding to a multiple of 4 plus 4.
     static constexpr int HL = (RAD + 3) / 4 * 4;
     static constexpr int CPITCH = (HL + kBandX + RAD + 3) / 4 * 4 + 4;
-    // Planes slab (bfloat16 elements): a hi part of SROWS rows of PB
-    // elements, then a lo part of the same shape (LO elements further on).
-    // Rows have an 8-element left margin and up to 8 right halo columns;
-    // halo columns move in pairs (HD dwords per side and plane).  With
-    // 16-wide tiles (8 dwords apart along a row, 4 per unit row) the pitch
-    // makes the 4 tile rows of a unit start 2 dwords apart modulo 8:
-    // R2 * PB / 2 = 2 (mod 8).  A pitch that is a multiple of 8 keeps every
-    // row 16-byte aligned (LDS DMA in 16-byte pieces); otherwise rows move
-    // in 4-byte pieces.
+    // Planes slab: rows of RBD dwords in which hi and lo pairs alternate:
+    // dword 2m + p holds values 2m and 2m+1 of plane p (0 hi, 1 lo), counted
+    // from HLB values left of the band, so that one 8-byte read returns a B
+    // register's hi and lo parts.  A row holds HLB = 8 values of left
+    // margin, the band and 8 values on the right (272 dwords; RAD <= 8), all
+    // moved by the row's own 4-byte transfers.  16-wide tiles are 16 dwords
+    // apart along a row; the pitch puts the 8 tile rows of a unit 2 dwords
+    // apart modulo 32: R2 * RBD = 2 (mod 32).
     static constexpr int HLB = 8;
-    static constexpr int PB = !SQUARE ? 280 : R2 == 1 ? 276 : 274;
-    static constexpr bool PLANES_X4 = PB % 8 == 0;
-    static constexpr int LO = SROWS * PB;
-    static constexpr int HD = (RAD + 1) / 2;
-    static_assert(STATE == kStateF32 || 2 * HD <= HLB, "halo wider than the margin");
-    static_assert(PB >= HLB + kBandX + 2 * HD && PB % 2 == 0, "plane row pitch");
-    static_assert(!SQUARE || (R2 * PB / 2) % 8 == 2, "plane row pitch does not spread the banks");
-    // with an even radius every B register's two values share one dword
-    // (tile origins and pair columns are even)
+    static constexpr int RBD = TALL && R2 == 1 ? 290 : 273;
+    static_assert(STATE == kStateF32 || (RAD <= HLB && RBD >= 2 * HLB + kBandX),
+                  "planes slab row");
+    static_assert(!TALL || (R2 * RBD) % 32 == 2, "plane row pitch does not spread the banks");
+    // with an even radius every B register's two values share one dword of
+    // each plane (tile origins and pair columns are even)
     static constexpr bool PAIR_DWORD = STATE == kStatePlanes && RAD % 2 == 0;
-    // per slab: elements between consecutive source rows, left margin, bytes
-    static constexpr int ROW = STATE == kStateF32 ? CPITCH : PB;
+    // per slab: distance between consecutive source rows (FP32 values;
+    // planes bytes), left margin (values), bytes
+    static constexpr int ROW = STATE == kStateF32 ? CPITCH : 4 * RBD;
     static constexpr int MARGIN = STATE == kStateF32 ? HL : HLB;
-    static constexpr int SLAB_BYTES = STATE == kStateF32 ? SROWS * CPITCH * 4 : 2 * SROWS * PB * 2;
-    // halo dwords of one slab, and the staging strip they land in (whole
-    // 512-lane transfers)
-    static constexpr int HALO_ROW = STATE == kStateF32 ? 2 * RAD : 4 * HD;
+    static constexpr int SLAB_BYTES = STATE == kStateF32 ? SROWS * CPITCH * 4 : SROWS * RBD * 4;
+    // FP32 halo dwords of one slab, and the staging strip they land in
+    // (whole 512-lane transfers); the planes rows carry their own halo
+    static constexpr int HALO_ROW = STATE == kStateF32 ? 2 * RAD : 0;
     static constexpr int NHALO = SROWS * HALO_ROW;
     static constexpr int HOPS = (NHALO + kThreads - 1) / kThreads;
     static constexpr int HSTRIP = HOPS * kThreads;
@@ -74,6 +72,13 @@ struct MmaGeom {
     static constexpr int NSLAB = 4 * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes ? 4 : 3;
     static_assert(NSLAB * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes, "slabs exceed LDS");
 };
+
+// Element index (16-bit units) of value column col of plane pl in planes
+// slab row r.
+template <int RBD>
+__host__ __device__ constexpr int planes_index(int r, int col, int pl) {
+    return 2 * (r * RBD + (col & ~1) + pl) + (col & 1);
+}
 
 // 3-D kernel: a work item is a column of the grid (a 256-column band of
 // WGH rows) over a range of z planes; the workgroup marches through z with a

@@ -144,10 +144,9 @@ struct Pipe {
     using G = MmaGeom<R1, R2, RAD, STATE>;
     static constexpr int DRW = (G::SROWS + kWaves - 1) / kWaves;      // slab rows each wave loads
     // LDS-DMA operations per slab row: FP32 one 16-byte transfer per lane
-    // (or four 4-byte ones when rows are not 16-byte aligned); planes one
-    // 16-byte transfer per half wave and plane
-    static constexpr int DMA_PER_ROW =
-        STATE == kStatePlanes ? (G::PLANES_X4 ? 2 : 2 * kBandX / 128) : (VEC ? 1 : kBandX / 64);
+    // (or four 4-byte ones when rows are not 16-byte aligned); planes four
+    // 4-byte transfers per lane and one by 16 lanes (272 dwords)
+    static constexpr int DMA_PER_ROW = STATE == kStatePlanes ? 5 : (VEC ? 1 : kBandX / 64);
     static constexpr int D = DRW * DMA_PER_ROW + G::HOPS;               // VMEM loads per wave per item
     static constexpr int STORES_PER_MB = STATE == kStatePlanes ? 2 : (VEC ? 1 : 4);
     static constexpr int M = G::U * G::MB * STORES_PER_MB;              // VMEM stores per wave per item
@@ -183,11 +182,11 @@ __device__ inline unsigned lds_addr_of(const void *p) {
 
 // Issue the loads of one work item.  FP32: the 256 interior columns of every
 // slab row (one 64-lane 16-byte transfer per row, or four 64-lane 4-byte
-// transfers when rows are not 16-byte aligned).  Planes: per source row, the
-// hi plane's 256 interior values by the lower half wave and the lo plane's by
-// the upper half, each into its own slab row.  Halo columns go to a staging
-// strip by 4-byte transfers (put_halo moves them into place).  Rows or
-// columns outside a zero-halo grid read from a zero page.  Every wave issues
+// transfers when rows are not 16-byte aligned); halo columns go to a staging
+// strip by 4-byte transfers (put_halo moves them into place).  Planes: each
+// slab row, halo included, by 4-byte transfers whose lanes alternate between
+// the hi and the lo plane.  Rows or columns outside a zero-halo grid read
+// from a zero page.  Every wave issues
 // the same number of transfers for every item (item and row indices are
 // clamped), which is what the explicit waits count on.
 template <int R1, int R2, int RAD, int STATE, bool VEC, int BC>
@@ -206,33 +205,21 @@ __device__ inline void issue_item(const void *zero_block, const MmaJob &g, char 
         const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
         const bool row_ok = BC != kBcZero || (gy >= 0 && gy < g.ny);
         if constexpr (STATE == kStatePlanes) {
-            // 8 values (16 bytes) per lane; rows are a multiple of 8 values
+            // dword 64h + lane of the row: plane lane & 1, values
+            // X0 - HLB + 64h + (lane & ~1) and the next (rows are a multiple
+            // of 8 values, so a pair is all in or all out of the grid)
             const unsigned short *in = static_cast<const unsigned short *>(g.in);
             const size_t plane = (size_t)g.ny * g.nx;
-            const int half = lane >> 5, l32 = lane & 31;
-            const int gx = wrap<BC>(X0 + 8 * l32, g.nx);
-            const bool ok = BC != kBcZero || (row_ok && gx < g.nx);
-            const void *src = ok ? (const void *)(in + half * plane + (size_t)gy * g.nx + gx)
-                                 : (const void *)(zeros + 16 * l32);
-            const unsigned short *srow = reinterpret_cast<const unsigned short *>(slab) + r * G::PB + G::HLB;
-            const unsigned dst_hi = lds_addr_of(srow);
-            const unsigned dst_lo = lds_addr_of(srow + G::LO);
-            if constexpr (G::PLANES_X4) {
-                // lanes 32..63 land at M0 + 16*lane, i.e. 512 bytes past M0
-                if (half == 0) lds_dma16(src, dst_hi);
-                else lds_dma16(src, dst_lo - 512);
-            } else {
-                // 4-byte pieces: two values per lane, 128 values per transfer
+            const unsigned dst = lds_addr_of(slab + r * G::RBD * 4);
 #pragma unroll
-                for (int pl = 0; pl < 2; ++pl)
-#pragma unroll
-                    for (int h = 0; h < kBandX / 128; ++h) {
-                        const int gx2 = wrap<BC>(X0 + 128 * h + 2 * lane, g.nx);
-                        const bool ok2 = BC != kBcZero || (row_ok && gx2 < g.nx);
-                        const void *src2 = ok2 ? (const void *)(in + pl * plane + (size_t)gy * g.nx + gx2)
-                                               : (const void *)(zeros + 4 * lane);
-                        lds_dma4(src2, (pl ? dst_lo : dst_hi) + 256 * h);
-                    }
+            for (int h = 0; h < 5; ++h) {
+                if (h < 4 || lane < 16) {
+                    const int gx = wrap<BC>(X0 - G::HLB + 64 * h + (lane & ~1), g.nx);
+                    const bool ok = BC != kBcZero || (row_ok && gx >= 0 && gx < g.nx);
+                    const void *src = ok ? (const void *)(in + (lane & 1) * plane + (size_t)gy * g.nx + gx)
+                                         : (const void *)(zeros + 4 * lane);
+                    lds_dma4(src, dst + 256 * h);
+                }
             }
         } else {
             const float *in = static_cast<const float *>(g.in);
@@ -260,22 +247,10 @@ __device__ inline void issue_item(const void *zero_block, const MmaJob &g, char 
         const int e = min(base + lane, G::NHALO - 1);
         const int r = e / G::HALO_ROW, j = e % G::HALO_ROW;
         const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
-        const void *src;
-        if constexpr (STATE == kStatePlanes) {
-            // pairs of values: plane, side, pair index
-            const int pl = j / (2 * G::HD), jj = j % (2 * G::HD);
-            const int t = jj % G::HD;
-            const int gx = wrap<BC>(jj < G::HD ? X0 - 2 * G::HD + 2 * t : X0 + kBandX + 2 * t, g.nx);
-            const bool ok = BC != kBcZero || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx);
-            const unsigned short *in = static_cast<const unsigned short *>(g.in);
-            src = ok ? (const void *)(in + pl * ((size_t)g.ny * g.nx) + (size_t)gy * g.nx + gx)
-                     : (const void *)(zeros + 4 * lane);
-        } else {
-            const int gx = wrap<BC>(j < RAD ? X0 - RAD + j : X0 + kBandX + (j - RAD), g.nx);
-            const bool ok = BC != kBcZero || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx);
-            const float *in = static_cast<const float *>(g.in);
-            src = ok ? (const void *)(in + (size_t)gy * g.nx + gx) : (const void *)(zeros + 4 * lane);
-        }
+        const int gx = wrap<BC>(j < RAD ? X0 - RAD + j : X0 + kBandX + (j - RAD), g.nx);
+        const bool ok = BC != kBcZero || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx);
+        const float *in = static_cast<const float *>(g.in);
+        const void *src = ok ? (const void *)(in + (size_t)gy * g.nx + gx) : (const void *)(zeros + 4 * lane);
         lds_dma4(src, lds_addr_of(strip + base));
     }
 }
@@ -286,15 +261,8 @@ __device__ inline void put_halo(char *slab, const unsigned *strip) {
     using G = MmaGeom<R1, R2, RAD, STATE>;
     for (int e = threadIdx.x; e < G::NHALO; e += kThreads) {
         const int r = e / G::HALO_ROW, j = e % G::HALO_ROW;
-        if constexpr (STATE == kStatePlanes) {
-            const int pl = j / (2 * G::HD), jj = j % (2 * G::HD);
-            const int t = jj % G::HD;
-            const int c = jj < G::HD ? G::HLB - 2 * G::HD + 2 * t : G::HLB + kBandX + 2 * t;
-            reinterpret_cast<unsigned *>(slab)[(pl * G::LO + r * G::PB + c) / 2] = strip[e];
-        } else {
-            const int c = j < RAD ? G::HL - RAD + j : G::HL + kBandX + (j - RAD);
-            reinterpret_cast<unsigned *>(slab)[r * G::CPITCH + c] = strip[e];
-        }
+        const int c = j < RAD ? G::HL - RAD + j : G::HL + kBandX + (j - RAD);
+        reinterpret_cast<unsigned *>(slab)[r * G::CPITCH + c] = strip[e];
     }
 }
 
@@ -348,10 +316,11 @@ __device__ inline void compute_item(float inv_sigma, const MmaJob &g, const char
             acc1[mb] = f4{0.f, 0.f, 0.f, 0.f};
             acc2[mb] = f4{0.f, 0.f, 0.f, 0.f};
         }
-        // byte address of the tile's patch origin in the slab (hi rows for
-        // the planes state); gather offsets are in bytes from it
-        constexpr int ES = STATE == kStatePlanes ? 2 : 4;
-        const int tbo = (srow0 * G::ROW + (G::MARGIN - RAD) + nbc * G::UW + tx_t * R1) * ES;
+        // byte address in the slab of the tile's patch origin (planes: of the
+        // dword pair holding its first column); gather offsets are in bytes
+        // from it
+        const int c0 = G::MARGIN - RAD + nbc * G::UW + tx_t * R1;
+        const int tbo = STATE == kStatePlanes ? srow0 * G::ROW + (c0 >> 1) * 8 : (srow0 * G::ROW + c0) * 4;
         const char *tb = slab + tbo;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
@@ -360,18 +329,20 @@ __device__ inline void compute_item(float inv_sigma, const MmaJob &g, const char
 #pragma unroll
                 for (int v = 0; v < VPK; ++v) {
                     if constexpr (G::PAIR_DWORD) {
+                        // hi and lo dwords of the pair, side by side
                         const unsigned *w = reinterpret_cast<const unsigned *>(tb + gather_off<VPK>(off2[kc], v, salt + u));
                         bh[v] = w[0];
-                        bl[v] = w[G::LO / 2];
+                        bl[v] = w[1];
                     } else {
-                        // the pair may start at an odd value: two dwords and
-                        // a byte align (offset arithmetic stays relative to
-                        // the slab, so the reads remain LDS reads)
+                        // the pair may start at an odd value (offset bit 1):
+                        // two dword pairs and a byte align (offset arithmetic
+                        // stays relative to the slab, so the reads remain LDS
+                        // reads)
                         const int ai = tbo + gather_off<VPK>(off2[kc], v, salt + u);
                         const unsigned *w = reinterpret_cast<const unsigned *>(slab + (ai & ~3));
                         const unsigned sh = (unsigned)(ai & 2);
-                        bh[v] = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
-                        bl[v] = __builtin_amdgcn_alignbyte(w[G::LO / 2 + 1], w[G::LO / 2], sh);
+                        bh[v] = __builtin_amdgcn_alignbyte(w[2], w[0], sh);
+                        bl[v] = __builtin_amdgcn_alignbyte(w[3], w[1], sh);
                     }
                 }
             } else {
@@ -527,7 +498,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
 #pragma unroll 1
     for (int s = 0;; ++s) {
         // wait for item s's transfers (every wave's, after the barrier),
-        // move its halo into place, refill the slab item s-1 used with item
+        // move an FP32 halo into place, refill the slab item s-1 used with item
         // s+NS-1, multiply item s
         switch (s) {
             case 0: wait_vmcnt<P::template W<0>>(); break;
@@ -537,9 +508,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2d(MmaArgs p) {
         }
         const int cur = s % NS;
         __builtin_amdgcn_s_barrier();
-        put_halo<R1, R2, RAD, STATE>(slab(cur), strip(cur));
-        __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0): halo writes done
-        __builtin_amdgcn_s_barrier();
+        if constexpr (G::NHALO > 0) {
+            put_halo<R1, R2, RAD, STATE>(slab(cur), strip(cur));
+            __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0): halo writes done
+            __builtin_amdgcn_s_barrier();
+        }
         issue(s + NS - 1);
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
@@ -585,7 +558,8 @@ static hipError_t launch_mma2d(MmaArgs &a, hipStream_t s) {
         items += ((g.nx + kBandX - 1) / kBandX) * ((g.ny + G::WGH - 1) / G::WGH);
         vec = vec && (g.nx % (STATE == kStatePlanes ? 8 : 4)) == 0;
         // one wrap suffices when every index is within one grid length
-        wrap1 = wrap1 && g.ny >= G::SROWS && g.nx >= kBandX + 2 * RAD + 2;
+        wrap1 = wrap1 && g.ny >= G::SROWS &&
+                g.nx >= kBandX + (STATE == kStatePlanes ? 2 * G::HLB : 2 * RAD + 2);
     }
     a.total_items = items;
     if (items == 0) return hipSuccess;

@@ -51,11 +51,12 @@ bool valid_star(const std::vector<double> &w, int ndim, int r) {
 // Fill the MMA kernel tables for the kernel's K order `kperm` (A' column per
 // K slot, kZeta for zero columns).  Sparse: compressed A'' in the SMFMAC
 // operand layout with its index words; dense: A' columns in kperm order.
-// Gather offsets are in bytes (elem_bytes per state element) from the tile's
-// patch origin within one input plane of the slab, whose rows are `pitch`
-// elements apart (the 3-D kernel picks the plane per K chunk).
+// Gather offsets are in bytes from the tile's patch origin within one input
+// plane of the slab: FP32 rows `pitch` values apart (the 3-D kernel picks the
+// plane per K chunk), or bfloat16 planes rows of interleaved hi/lo dword
+// pairs `pitch` bytes apart.
 ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<int> &kperm, int mode, int part,
-                           int kc_count, int pitch, int elem_bytes, std::vector<uint8_t> *blob, size_t *off_hi,
+                           int kc_count, int pitch, bool planes, std::vector<uint8_t> *blob, size_t *off_hi,
                            size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
     const int MB = gm.m_prime() / 16;
     const std::vector<double> amat = morph_matrix(gm, p->w);
@@ -116,7 +117,18 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
                 int32_t o = 0;
                 if (col != kZeta) {
                     const int pr = (col % plane) / gm.g, pc = col % gm.g;
-                    o = (pr * pitch + pc) * elem_bytes;
+                    if (planes) {
+                        // slab rows of interleaved hi/lo dword pairs (pitch
+                        // in bytes): value column c sits at byte
+                        // 8 * (c / 2) + 2 * (c % 2) of the row (hi; lo 4
+                        // bytes on), counted from the dword pair of the tile
+                        // origin, whose parity is that of the radius (the
+                        // slab margin is even)
+                        const int c = (p->rad & 1) + pc;
+                        o = pr * pitch + (c >> 1) * 8 + (c & 1) * 2;
+                    } else {
+                        o = (pr * pitch + pc) * 4;
+                    }
                 }
                 // the kernels keep two offsets per 32-bit register
                 if (o >= 65536) return SS_E_UNSUPPORTED;
@@ -249,11 +261,11 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     if (!mma2d_geometry(key, &wgh, &row)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, p->perm, mode, part, key.kc, row, state == kStatePlanes ? 2 : 4, &blob, &o_hi,
+    st = build_mma_tables(p, gm, p->perm, mode, part, key.kc, row, state == kStatePlanes, &blob, &o_hi,
                           &o_lo, &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
-    // the planes kernels of an even radius read each B register as one
-    // dword: every gather offset must be a whole dword
+    // the planes kernels of an even radius read each B register's hi and lo
+    // parts as one dword each: every gather offset must be a whole dword
     if (state == kStatePlanes && p->rad % 2 == 0)
         for (int32_t o : p->kernel_lut)
             if (o % 4) return SS_E_UNSUPPORTED;
@@ -350,7 +362,7 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     if (!mma3d_geometry(*key, &wgh, &pitch)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, 4, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
                           &o_zero);
     if (st != SS_OK) return st;
     st = upload(p, blob);
