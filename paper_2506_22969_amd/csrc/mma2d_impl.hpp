@@ -241,6 +241,7 @@ __device__ inline void issue_item(const void *zero_block, const MmaJob &g, char 
             }
         }
     }
+    if constexpr (G::NHALO > 0) {
 #pragma unroll
     for (int h = 0; h < G::HOPS; ++h) {
         const int base = (h * kWaves + wave) * 64;
@@ -253,12 +254,14 @@ __device__ inline void issue_item(const void *zero_block, const MmaJob &g, char 
         const void *src = ok ? (const void *)(in + (size_t)gy * g.nx + gx) : (const void *)(zeros + 4 * lane);
         lds_dma4(src, lds_addr_of(strip + base));
     }
+    }
 }
 
 // Move an item's halo columns from the staging strip into the slab.
 template <int R1, int R2, int RAD, int STATE>
 __device__ inline void put_halo(char *slab, const unsigned *strip) {
     using G = MmaGeom<R1, R2, RAD, STATE>;
+    static_assert(G::NHALO > 0, "FP32 slabs only");
     for (int e = threadIdx.x; e < G::NHALO; e += kThreads) {
         const int r = e / G::HALO_ROW, j = e % G::HALO_ROW;
         const int c = j < RAD ? G::HL - RAD + j : G::HL + kBandX + (j - RAD);
