@@ -201,10 +201,23 @@ ss_status upload(ss_plan_ *p, const std::vector<uint8_t> &blob) {
 // State layout of a dtype on the MMA path.
 int mma_state(int dtype) { return dtype == SS_SPLIT_BF16 ? kStatePlanes : kStateF32; }
 
+// The slab-pipelined kernels (matrix-core and LDS direct) address a work
+// item's rows, and a 3-D plane's rows, with 32-bit offsets: a 2-D item of
+// kItemRows rows, or a 3-D plane, must span fewer than 2^31 bytes.  Larger
+// grids run on the plain direct kernel (64-bit indexing).
+bool slab_offsets_fit(const ss_plan_ *p) {
+    const int64_t nx = p->dims[2], ny = p->dims[1];
+    const int64_t bytes = p->dtype == SS_F64 ? 8 : p->dtype == SS_SPLIT_BF16 ? 2 : 4;
+    const int64_t limit = (int64_t)1 << 31;
+    if (p->ndim == 3) return ny * nx * bytes < limit;
+    return (int64_t)kItemRows * nx * bytes < limit;
+}
+
 ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
     const int state = mma_state(p->dtype);
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    if (!slab_offsets_fit(p)) return SS_E_UNSUPPORTED;
     // the planes kernels move rows in 8-value (16-byte) pieces
     if (state == kStatePlanes && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
     ModelParams mp{};
@@ -314,6 +327,7 @@ bool pairs_adjacent(const Geometry &gm, const std::vector<int> &perm) {
 ss_status plan_mma3d(ss_plan_ *p, int engine) {
     const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    if (!slab_offsets_fit(p)) return SS_E_UNSUPPORTED;
     MmaKey keys[16];
     const int nkeys = mma3d_keys(p->rad, mode, part, keys, 16);
     const MmaKey *key = nullptr;
@@ -451,7 +465,7 @@ ss_status plan_direct(ss_plan_ *p) {
     // need rows of a multiple of 8 values); FP64, 1-D and 3-D on the plain one
     const int state = mma_state(p->dtype);
     MmaLaunch lds = nullptr;
-    if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0))
+    if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0) && slab_offsets_fit(p))
         lds = find_lds_direct2d(p->rad, state);
     const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
     const size_t o_zero = (wbytes + 255) & ~(size_t)255;

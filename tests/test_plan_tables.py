@@ -140,3 +140,19 @@ def test_planes_rows_must_be_a_multiple_of_8_for_mma():
         native.Plan("box", 1, w, (64, 60), "split_bf16", engine="smfmac", host_only=True)
     with native.Plan("box", 1, w, (64, 60), "split_bf16", host_only=True) as p:
         assert p.info["engine_name"] == "direct"
+
+
+def test_rows_beyond_32bit_item_offsets_fall_back_to_direct():
+    """A 2-D work item of 32 rows (or a 3-D plane) must span < 2^31 bytes for
+    the slab kernels; wider grids plan onto the direct engine."""
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
+    wide = (4, 1 << 24)                      # 32 rows x 2^24 x 4 bytes = 2^31
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w, wide, "f32_split_f16", engine="smfmac", host_only=True)
+    with native.Plan("box", 1, w, wide, "f32_split_f16", host_only=True) as p:
+        assert p.info["engine_name"] == "direct"
+    with native.Plan("box", 1, w, (4, (1 << 24) - 8), "f32_split_f16", engine="smfmac", host_only=True) as p:
+        assert p.info["engine_name"] == "smfmac"
+    w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w3, (3, 1 << 14, 1 << 15), "f32_split_f16", engine="smfmac", host_only=True)
