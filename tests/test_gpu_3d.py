@@ -55,6 +55,7 @@ CASES = [  # (shape, dims, boundary)
     ("star", (9, 17, 31), "periodic"),
     ("box", (3, 5, 7), "zero"),
     ("box", (40, 64, 520), "periodic"),
+    ("star", (12, 24, 258), "periodic"),   # narrowest rows for a single wrap, 4-byte row transfers
 ]
 
 

@@ -73,6 +73,7 @@ CASES = [  # (shape, radius, fuse, boundary, dims)
     ("star", 3, 2, "periodic", (96, 264)),
     ("box", 3, 2, "periodic", (100, 520)),
     ("star", 3, 2, "periodic", (16, 40)),
+    ("box", 1, 1, "periodic", (40, 272)),   # narrowest planes rows for a single wrap
 ]
 
 
