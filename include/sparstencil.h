@@ -115,7 +115,13 @@ enum {
     SS_Q_LUT = 7,         /* int32[K_pad][3]: (pz, pr, pc), -1s for zero cols    */
     SS_Q_MODEL = 8,       /* double[n][7]: r1, r2, T, T_compute, T_global,
                              T_shared, K_pad for every candidate layout          */
-    SS_Q_KERNEL_LUT = 9   /* int32[n]: LDS offsets the launched kernel gathers   */
+    SS_Q_KERNEL_LUT = 9,  /* int32[n]: LDS offsets the launched kernel gathers   */
+    SS_Q_KERNEL_PERM = 10 /* int32[n]: A' column per K slot of the launched
+                             matrix-core kernel, -1 = zero column: SS_Q_PERM's
+                             groups with the columns the stencil never uses
+                             dropped and re-paired (sparse), or the used column
+                             pairs in natural order (dense); empty for the
+                             direct engine                                        */
 };
 
 typedef struct {

@@ -359,6 +359,83 @@ def gather_lut(d: MorphDims, perm):
 
 
 # ----------------------------------------------------------------------------
+# 7b. structure-aware K orders of the kernels (beyond the paper)
+#
+# The paper's structure is the bounding box, so a star stencil's never-used
+# patch columns still occupy K.  This build's reading for the kernels: a
+# column is used when some row of A' holds a nonzero value in it.  Sparse
+# order: walk Algorithm 1's groups; each group is two dominoes (slots 0-1 and
+# 2-3, horizontally adjacent columns feeding one 32-bit B register).  Keep a
+# group when both dominoes hold a used column, drop it when neither does,
+# otherwise set its used domino aside.  Then, in the order they were set
+# aside, give each unpaired domino the first later unpaired domino whose
+# columns share no nonzero row with its own, position by position (the two
+# halves of the new group are then Definition-1 conflict-free pairs), or a
+# domino of zero columns.  Kept groups come first, new groups after, zero
+# columns up to the fragment's K.  Dense order: the natural column order in
+# pairs (c, c+1), c even, keeping the pairs that hold a used column, zero
+# columns up to the fragment's K.
+
+def used_columns(a: np.ndarray) -> np.ndarray:
+    """Columns of A' with a nonzero value in some row."""
+    return np.array([bool(np.count_nonzero(a[:, c])) for c in range(a.shape[1])])
+
+
+def compact_sparse_order(a: np.ndarray, perm, kfrag: int):
+    used = used_columns(a)
+
+    def holds_used(domino):
+        return any(c != ZETA and used[c] for c in domino)
+
+    def rows_of(c):
+        return set() if c == ZETA else set(np.flatnonzero(a[:, c]))
+
+    kept, aside = [], []
+    for j in range(0, len(perm), 4):
+        first, second = tuple(perm[j:j + 2]), tuple(perm[j + 2:j + 4])
+        u1, u2 = holds_used(first), holds_used(second)
+        if u1 and u2:
+            kept.append(list(perm[j:j + 4]))
+        elif u1:
+            aside.append(first)
+        elif u2:
+            aside.append(second)
+    paired = [False] * len(aside)
+    new = []
+    for i, dom in enumerate(aside):
+        if paired[i]:
+            continue
+        paired[i] = True
+        partner = (ZETA, ZETA)
+        for j in range(i + 1, len(aside)):
+            if paired[j]:
+                continue
+            other = aside[j]
+            if not (rows_of(dom[0]) & rows_of(other[0])) and not (rows_of(dom[1]) & rows_of(other[1])):
+                partner = other
+                paired[j] = True
+                break
+        new.append([dom[0], dom[1], partner[0], partner[1]])
+    out = [c for grp in kept + new for c in grp]
+    while len(out) % kfrag:
+        out.append(ZETA)
+    return out
+
+
+def compact_dense_order(a: np.ndarray, kfrag: int):
+    used = used_columns(a)
+    kp = a.shape[1]
+    out = []
+    for c in range(0, kp, 2):
+        pair = [c, c + 1 if c + 1 < kp else ZETA]
+        if any(x != ZETA and used[x] for x in pair):
+            out.extend(pair)
+    while len(out) % kfrag:
+        out.append(ZETA)
+    return out
+
+
+# ----------------------------------------------------------------------------
 # 8. layout exploration model (Section 3.3, Eqs. 6-11)
 
 @dataclass(frozen=True)

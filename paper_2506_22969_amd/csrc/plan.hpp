@@ -22,6 +22,7 @@ struct ss_plan_ {
     std::vector<int32_t> lut;
     std::vector<double> model;        // rows of 7
     std::vector<int32_t> kernel_lut;
+    std::vector<int32_t> kperm;       // A' column per K slot of the launched kernel
     // device
     void *dev = nullptr;
     ss::MmaArgs margs{};

@@ -120,10 +120,81 @@ std::vector<int> group_pairs(const PairList &pl, int kfrag) {
     return perm;
 }
 
+static std::vector<char> used_columns(const Geometry &gm, const std::vector<double> &amat) {
+    const int mp = gm.m_prime(), kp = gm.k_prime();
+    std::vector<char> used(kp, 0);
+    for (int row = 0; row < mp; ++row)
+        for (int c = 0; c < kp; ++c)
+            if (amat[(size_t)row * kp + c] != 0.0) used[c] = 1;
+    return used;
+}
+
+std::vector<int> compact_groups(const Geometry &gm, const std::vector<double> &amat, const std::vector<int> &perm,
+                                int kfrag) {
+    const int mp = gm.m_prime(), kp = gm.k_prime();
+    const std::vector<char> used = used_columns(gm, amat);
+    auto is_used = [&](int c) { return c != kZeta && used[c]; };
+    // columns a and b may share a 2:4 half when no row is nonzero in both
+    auto apart = [&](int a, int b) {
+        if (a == kZeta || b == kZeta) return true;
+        for (int row = 0; row < mp; ++row)
+            if (amat[(size_t)row * kp + a] != 0.0 && amat[(size_t)row * kp + b] != 0.0) return false;
+        return true;
+    };
+    std::vector<int> out;
+    std::vector<std::pair<int, int>> half;   // used dominoes of half-used groups
+    for (size_t j = 0; j + 3 < perm.size(); j += 4) {
+        const bool ua = is_used(perm[j]) || is_used(perm[j + 1]);
+        const bool ub = is_used(perm[j + 2]) || is_used(perm[j + 3]);
+        if (ua && ub) out.insert(out.end(), perm.begin() + j, perm.begin() + j + 4);
+        else if (ua) half.emplace_back(perm[j], perm[j + 1]);
+        else if (ub) half.emplace_back(perm[j + 2], perm[j + 3]);
+    }
+    std::vector<char> taken(half.size(), 0);
+    for (size_t i = 0; i < half.size(); ++i) {
+        if (taken[i]) continue;
+        taken[i] = 1;
+        int mate = -1;
+        for (size_t j = i + 1; j < half.size() && mate < 0; ++j)
+            if (!taken[j] && apart(half[i].first, half[j].first) && apart(half[i].second, half[j].second))
+                mate = (int)j;
+        out.push_back(half[i].first);
+        out.push_back(half[i].second);
+        if (mate >= 0) {
+            taken[mate] = 1;
+            out.push_back(half[mate].first);
+            out.push_back(half[mate].second);
+        } else {
+            out.push_back(kZeta);
+            out.push_back(kZeta);
+        }
+    }
+    while (out.size() % (size_t)kfrag) out.push_back(kZeta);
+    return out;
+}
+
+std::vector<int> dense_order(const Geometry &gm, const std::vector<double> &amat, int kfrag) {
+    const int kp = gm.k_prime();
+    const std::vector<char> used = used_columns(gm, amat);
+    std::vector<int> out;
+    for (int c = 0; c < kp; c += 2) {
+        const bool u = used[c] || (c + 1 < kp && used[c + 1]);
+        if (!u) continue;
+        out.push_back(c);
+        out.push_back(c + 1 < kp ? c + 1 : kZeta);
+    }
+    while (out.size() % (size_t)kfrag) out.push_back(kZeta);
+    return out;
+}
+
 bool compress(const Geometry &gm, const std::vector<double> &amat, const std::vector<int> &perm,
-              Compressed *out) {
+              Compressed *out, bool by_value) {
     const int mp = gm.m_prime(), kp = gm.k_prime();
     const int groups = (int)perm.size() / 4;
+    auto live_at = [&](int row, int c) {
+        if (c == kZeta) return false;
+        return by_value ? amat[(size_t)row * kp + c] != 0.0 : structural(gm, row, c);
+    };
     out->values.assign((size_t)mp * groups * 2, 0.0);
     out->meta.assign((size_t)mp * groups * 2, 0);
     for (int row = 0; row < mp; ++row) {
@@ -131,7 +202,7 @@ bool compress(const Geometry &gm, const std::vector<double> &amat, const std::ve
             int live[4], nlive = 0;
             for (int p = 0; p < 4; ++p) {
                 const int c = perm[4 * j + p];
-                if (c != kZeta && structural(gm, row, c)) live[nlive++] = p;
+                if (live_at(row, c)) live[nlive++] = p;
             }
             if (nlive > 2) return false;
             int pos[2], n = 0;
@@ -145,7 +216,7 @@ bool compress(const Geometry &gm, const std::vector<double> &amat, const std::ve
             for (int t = 0; t < 2; ++t) {
                 const int c = perm[4 * j + pos[t]];
                 double v = 0.0;
-                if (c != kZeta && structural(gm, row, c)) v = amat[(size_t)row * kp + c];
+                if (live_at(row, c)) v = amat[(size_t)row * kp + c];
                 out->values[((size_t)row * groups + j) * 2 + t] = v;
                 out->meta[((size_t)row * groups + j) * 2 + t] = (uint8_t)pos[t];
             }

@@ -48,13 +48,15 @@ PairList matrix_pairs(const Geometry &gm);
 // columns to a multiple of kfrag.
 std::vector<int> group_pairs(const PairList &pl, int kfrag);
 
-// Compressed values and positions (i0 < i1) per row and 4-group.
+// Compressed values and positions (i0 < i1) per row and 4-group.  The
+// positions kept are a row's structural ones (bounding box), or with
+// by_value its nonzero ones (the kernels' compacted orders rely on that).
 struct Compressed {
     std::vector<double> values;   // m' x K_pad/2
     std::vector<uint8_t> meta;    // m' x K_pad/4 x 2
 };
 bool compress(const Geometry &gm, const std::vector<double> &amat, const std::vector<int> &perm,
-              Compressed *out);
+              Compressed *out, bool by_value = false);
 
 // Round-to-nearest-even of an FP64 value into binary16 / bfloat16 bits.
 // Returns false on overflow.
@@ -80,6 +82,22 @@ struct ModelParams {
 };
 ModelRow model_time(const ModelParams &mp, int r1, int r2);
 bool model_better(const ModelRow &a, const ModelRow &b);
+
+// Structure-aware K order for the kernels (beyond the paper's bounding-box
+// structure): a patch column is used
+// when some row of A' holds a nonzero in it.  Sparse: the 4-groups of `perm`
+// are kept when both their dominoes (slots 0-1 and 2-3, each a horizontally
+// adjacent column pair) hold a used column, dropped when neither does, and
+// the used dominoes of the remaining groups are re-paired first fit, in
+// order, with the first later domino whose two columns share no nonzero row
+// with theirs (else with a zero domino); kept groups first, then the new
+// ones, zero groups up to a multiple of kfrag.  Dense: the column pairs
+// (c, c+1), c even, of the natural order that hold a used column, zero
+// columns up to a multiple of kfrag.  With every column used (box stencils)
+// both return the plain orders.
+std::vector<int> compact_groups(const Geometry &gm, const std::vector<double> &amat, const std::vector<int> &perm,
+                                int kfrag);
+std::vector<int> dense_order(const Geometry &gm, const std::vector<double> &amat, int kfrag);
 
 // Every 32-bit B register of the sparse kernel holds two K slots that are
 // either both zero columns or horizontally adjacent patch elements starting

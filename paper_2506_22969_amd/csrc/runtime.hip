@@ -76,7 +76,7 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
     std::vector<int32_t> boff((size_t)kc_count * 4 * VPK, 0);
     if (mode == kSparse) {
         Compressed cm;
-        if (!compress(gm, amat, kperm, &cm)) return SS_E_UNSUPPORTED;
+        if (!compress(gm, amat, kperm, &cm, true)) return SS_E_UNSUPPORTED;
         const int groups = (int)kperm.size() / 4;
         for (int mb = 0; mb < MB; ++mb)
             for (int kc = 0; kc < kc_count; ++kc)
@@ -213,6 +213,15 @@ bool slab_offsets_fit(const ss_plan_ *p) {
     return (int64_t)kItemRows * nx * bytes < limit;
 }
 
+// K order of a 2-D matrix-core kernel: Algorithm 1's groups compacted to the
+// columns the stencil uses (sparse), or the used column pairs in natural
+// order (dense).
+std::vector<int> kernel_order(const ss_plan_ *p, const Geometry &gm, int mode) {
+    const std::vector<double> amat = morph_matrix(gm, p->w);
+    if (mode == kSparse) return compact_groups(gm, amat, group_pairs(matrix_pairs(gm), 64), 64);
+    return dense_order(gm, amat, 32);
+}
+
 ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
     const int state = mma_state(p->dtype);
@@ -237,12 +246,9 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
         const MmaKey &c = keys[i];
         if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
         const Geometry gm = make_geometry(2, p->k, c.r1, c.r2);
-        if (mode == kSparse) {
-            const std::vector<int> perm = group_pairs(matrix_pairs(gm), 64);
-            if (!pair_aligned(gm, perm) || (int)perm.size() != 64 * c.kc) continue;
-        } else {
-            if (gm.g % 2 || (gm.k_prime() + 31) / 32 != c.kc) continue;
-        }
+        if (mode == kDense && gm.g % 2) continue;
+        if (mode == kSparse && !pair_aligned(gm, group_pairs(matrix_pairs(gm), 64))) continue;
+        if ((int)kernel_order(p, gm, mode).size() != (mode == kSparse ? 64 : 32) * c.kc) continue;
         cands.push_back(c);
     }
     if (cands.empty()) return SS_E_UNSUPPORTED;
@@ -264,17 +270,14 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const Geometry gm = make_geometry(2, p->k, key.r1, key.r2);
     ss_status st = build_canonical(p, gm, part, 64);
     if (st != SS_OK) return st;
-    if (mode == kDense) {
-        // the dense engine consumes A' in natural column order
-        p->perm.clear();
-        const int kd = (gm.k_prime() + 31) / 32 * 32;
-        for (int c = 0; c < kd; ++c) p->perm.push_back(c < gm.k_prime() ? c : kZeta);
-    }
+    const std::vector<int> kperm = kernel_order(p, gm, mode);
+    if (mode == kSparse && !pair_aligned(gm, kperm)) return SS_E_UNSUPPORTED;
+    p->kperm.assign(kperm.begin(), kperm.end());
     int wgh, row;
     if (!mma2d_geometry(key, &wgh, &row)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, p->perm, mode, part, key.kc, row, state == kStatePlanes, &blob, &o_hi,
+    st = build_mma_tables(p, gm, kperm, mode, part, key.kc, row, state == kStatePlanes, &blob, &o_hi,
                           &o_lo, &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
     // the planes kernels of an even radius read each B register's hi and lo
@@ -376,6 +379,7 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     if (!mma3d_geometry(*key, &wgh, &pitch)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    p->kperm.assign(kperm.begin(), kperm.end());
     st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
                           &o_zero);
     if (st != SS_OK) return st;
@@ -751,6 +755,7 @@ ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *n
         case SS_Q_LUT: return copy_out(p->lut, buf, nbytes);
         case SS_Q_MODEL: return copy_out(p->model, buf, nbytes);
         case SS_Q_KERNEL_LUT: return copy_out(p->kernel_lut, buf, nbytes);
+        case SS_Q_KERNEL_PERM: return copy_out(p->kperm, buf, nbytes);
         default: return SS_E_INVALID;
     }
 }

@@ -23,7 +23,7 @@ DTYPES = {"f64": 0, "f32": 1, "f16": 2, "f32_split_f16": 3, "f32_split_bf16": 4,
 BOUNDARIES = {"zero": 0, "periodic": 1}
 ENGINES = {"auto": 0, "smfmac": 1, "mfma": 2, "direct": 3}
 ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
-(Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT) = range(10)
+(Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM) = range(11)
 
 EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
            "sparstencil_sweep", "sparstencil_launch_count", "sparstencil_grid_bytes",
@@ -275,7 +275,7 @@ class Plan:
         raw = sparstencil_plan_query(self.handle, what)
         dt = {Q_COEFFS: np.float64, Q_PERM: np.int32, Q_VALUES: np.float64, Q_META: np.uint8,
               Q_HI: np.uint16, Q_LO: np.uint16, Q_LUT: np.int32, Q_MODEL: np.float64,
-              Q_KERNEL_LUT: np.int32}[what]
+              Q_KERNEL_LUT: np.int32, Q_KERNEL_PERM: np.int32}[what]
         return np.frombuffer(raw, dtype=dt).copy()
 
     def run(self, inp, out, steps, stream=None):

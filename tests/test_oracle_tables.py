@@ -339,3 +339,92 @@ def test_composed_sum_is_power_of_sum():
     c = T.compose(w, 3)
     assert c.sum() == 1.0           # dyadic, exact
     assert c.shape == (7, 7)
+
+
+# ----------------------------------------------------------------------------
+# structure-aware kernel orders (beyond the paper's bounding-box structure)
+
+def _star_w(radius, fuse, seed=45):
+    w, _ = synthetic.random_coeffs("star", radius, 2, seed=seed, grid_shape=(64, 64))
+    w = np.asarray(w, dtype=np.float64)
+    return T.compose(w, fuse) if fuse > 1 else w
+
+
+@pytest.mark.parametrize("k,r1,r2", [(3, 8, 8), (7, 8, 8), (13, 16, 2), (7, 8, 4)])
+def test_compaction_is_identity_for_box_stencils(k, r1, r2):
+    """A box stencil uses every patch column: both orders are the plain ones."""
+    w = synthetic.random_coeffs("box", (k - 1) // 2, 2, seed=7, grid_shape=(64, 64))[0]
+    a, s, d = T.morph(np.asarray(w, dtype=np.float64), r1, r2)
+    perm = T.group(T.plane_pairs(d)[0], 64)
+    assert T.compact_sparse_order(a, perm, 64) == perm
+    natural = list(range(d.k_prime)) + [T.ZETA] * (-d.k_prime % 32)
+    assert T.compact_dense_order(a, 32) == natural
+
+
+@pytest.mark.parametrize("radius,fuse,r1,r2", [(3, 1, 8, 8), (3, 1, 8, 4), (3, 1, 16, 2), (3, 2, 16, 2),
+                                                (3, 2, 16, 1), (3, 2, 8, 8), (2, 1, 8, 8), (1, 1, 8, 8)])
+def test_compacted_orders_are_complete_and_24_valid(radius, fuse, r1, r2):
+    """Brute force on A' itself: every used column appears exactly once, every
+    4-group holds at most two nonzeros per row, every B register is a zero
+    pair or two horizontally adjacent columns starting at an even column (the
+    sparse order keeps Algorithm 1's registers, so only where those are), and
+    K never grows."""
+    a, s, d = T.morph(_star_w(radius, fuse), r1, r2)
+    used = {c for c in range(d.k_prime) if np.any(a[:, c] != 0.0)}
+    perm = T.group(T.plane_pairs(d)[0], 64)
+
+    def registers_adjacent(order):
+        for kk in range(0, len(order), 2):
+            x, y = order[kk], order[kk + 1]
+            if x == T.ZETA and y == T.ZETA:
+                continue
+            if not (x != T.ZETA and y == x + 1 and (x % d.g) % 2 == 0):
+                return False
+        return True
+
+    for order, frag in [(T.compact_sparse_order(a, perm, 64), 64), (T.compact_dense_order(a, 32), 32)]:
+        assert len(order) % frag == 0
+        cols = [c for c in order if c != T.ZETA]
+        assert len(cols) == len(set(cols))
+        assert used <= set(cols)
+        if frag == 32 or registers_adjacent(perm):
+            assert registers_adjacent(order)
+        for kk in range(0, len(order), 2):
+            if order[kk] != T.ZETA or order[kk + 1] != T.ZETA:
+                assert order[kk] in used or order[kk + 1] in used
+    sparse = T.compact_sparse_order(a, perm, 64)
+    assert len(sparse) <= len(perm)
+    for j in range(0, len(sparse), 4):
+        cols = [c for c in sparse[j:j + 4] if c != T.ZETA]
+        assert np.all(np.count_nonzero(a[:, cols], axis=1) <= 2)
+
+
+def test_compaction_counts_fused_13_point_star_at_16x2():
+    """Two fused 13-point stars (radius 6, 61 points) at tile (16,2): the
+    28 x 14 patch uses all 28 columns of rows 6-7 (the centre row of the
+    stencil), columns 3..24 of rows 3-5 and 8-10 (|dy| <= 3 reaches |dx| <= 3)
+    and columns 6..21 of rows 0-2 and 11-13 (|dy| >= 4 only at dx = 0):
+    2*28 + 6*22 + 6*16 = 284 of 392 columns.  Algorithm 1 pairs block 0 with
+    block 13 (8 groups used, 6 empty) and the other blocks' columns t with
+    t + 14 (per row: rows 6-7 seven full groups; rows 3-5 and 8-10 five full,
+    two half used; rows 1-2 and 11-12 one full, six half used), so 56 groups
+    stay, 36 dominoes are re-paired and 6 groups go.  At most 36 new groups
+    and at least 18: between 74 and 92 groups, and the re-pairing must keep
+    it within 80 (K = 320, 5 chunks of 64 instead of 7)."""
+    a, s, d = T.morph(_star_w(3, 2), 16, 2)
+    used = [c for c in range(d.k_prime) if np.any(a[:, c] != 0.0)]
+    assert len(used) == 284
+    perm = T.group(T.plane_pairs(d)[0], 64)
+    assert len(perm) == 448
+    holds = lambda dom: any(c != T.ZETA and c in set(used) for c in dom)
+    kinds = [(holds(perm[j:j + 2]), holds(perm[j + 2:j + 4])) for j in range(0, len(perm), 4)
+             if any(c != T.ZETA for c in perm[j:j + 4])]
+    assert sum(1 for u in kinds if u[0] and u[1]) == 56
+    assert sum(1 for u in kinds if u[0] != u[1]) == 36
+    assert sum(1 for u in kinds if not u[0] and not u[1]) == 6
+    sparse = T.compact_sparse_order(a, perm, 64)
+    assert len(sparse) == 320
+    groups = [sparse[j:j + 4] for j in range(0, len(sparse), 4) if any(c != T.ZETA for c in sparse[j:j + 4])]
+    assert 74 <= len(groups) <= 80
+    assert groups[:56] == [perm[j:j + 4] for j in range(0, len(perm), 4)
+                           if holds(perm[j:j + 2]) and holds(perm[j + 2:j + 4])]

@@ -156,3 +156,29 @@ def test_rows_beyond_32bit_item_offsets_fall_back_to_direct():
     w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
     with pytest.raises(native.SparStencilError):
         native.Plan("box", 1, w3, (3, 1 << 14, 1 << 15), "f32_split_f16", engine="smfmac", host_only=True)
+
+
+@pytest.mark.parametrize("shape,radius,fuse,dtype,engine", [
+    ("star", 3, 2, "split_bf16", "smfmac"), ("star", 3, 2, "split_bf16", "mfma"),
+    ("star", 3, 1, "split_bf16", "smfmac"), ("star", 3, 1, "f32_split_f16", "mfma"),
+    ("star", 3, 1, "f32_split_bf16", "smfmac"), ("star", 1, 1, "f32_split_f16", "smfmac"),
+    ("box", 3, 2, "split_bf16", "smfmac"), ("box", 1, 1, "f32_split_f16", "mfma")])
+def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
+    """The launched kernel's K order (Algorithm 1's groups compacted to the
+    used columns, or the used column pairs in natural order) equals the
+    oracle's, bit for bit."""
+    dims = (256, 256)
+    w, _ = synthetic.random_coeffs(shape, radius, 2, seed=45 if radius == 3 else 1, grid_shape=dims)
+    kw = dict(boundary="periodic", fuse_steps=fuse) if fuse > 1 else {}
+    with native.Plan(shape, radius, w, dims, dtype, engine=engine, host_only=True, **kw) as p:
+        info = p.info
+        got = p.table(native.Q_KERNEL_PERM)
+        wk = p.table(native.Q_COEFFS).reshape(info["k"], info["k"])
+    a, s, d = T.morph(wk, info["r1"], info["r2"])
+    if engine == "smfmac":
+        ref = T.compact_sparse_order(a, T.group(T.plane_pairs(d)[0], 64), 64)
+    else:
+        ref = T.compact_dense_order(a, 32)
+    assert np.array_equal(got, np.array(ref, dtype=np.int32))
+    if shape == "star" and radius == 3:
+        assert len(ref) < (len(T.group(T.plane_pairs(d)[0], 64)) if engine == "smfmac" else -(-d.k_prime // 32) * 32)
