@@ -22,9 +22,10 @@
 // Gather: every 32-bit B register holds two horizontally adjacent patch
 // elements (the 4-group layout [P0.a, P1.a, P0.b, P1.b] puts the column-t and
 // column-(t+1) elements of a block pair side by side), so one two-dword LDS
-// read feeds one hi and one lo register (FP32 state), or one dword read per
-// plane (planes, even radius: the pair starts at an even column) or two and a
-// byte align (planes, odd radius).
+// read feeds one hi and one lo register: two FP32 values split in registers,
+// or, on the planes state whose slab rows interleave hi and lo dword pairs,
+// the pair's hi and lo dwords (even radius: the pair starts at an even
+// column), or two such reads and two byte aligns (odd radius).
 #pragma once
 
 #include <hip/hip_runtime.h>
