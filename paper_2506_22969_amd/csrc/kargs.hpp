@@ -84,6 +84,10 @@ int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max);
 // bfloat16 planes); nullptr when no kernel exists for the radius.
 MmaLaunch find_lds_direct2d(int rad, int state);
 
+// Direct 3-D sweep (FP32 state) from the same z-march pipeline as the 3-D
+// matrix kernels; nullptr when no kernel exists for the radius.
+MmaLaunch find_lds_direct3d(int rad);
+
 // Dense FP64 MMA sweep (tile 8 x 4, FP64 state and coefficients): the
 // launch for radius `rad` and KC chunks of 4, and its slab row pitch.
 MmaLaunch find_mma2d_f64(int rad, int kc);

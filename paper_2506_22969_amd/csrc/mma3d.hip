@@ -307,6 +307,149 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     }
 }
 
+// Direct 3-D sweep on the vector ALUs (the same-box baseline without the
+// matrix product), fed by the same z-march pipeline: thread t computes column
+// t % 256 of the 256 x 16 item, rows 8 (t / 256) .. + 7.  Each input plane
+// adds its contributions to the 2r+1 output planes it feeds (rotating
+// accumulators, as in the matrix kernel), one slab column in registers at a
+// time, with FP32 fused multiply-adds and coefficients from an LDS copy.
+constexpr int kD3Rows = 8;   // output rows per thread
+
+template <int RAD, bool VEC, int BC>
+__global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
+    using G = Mma3Geom<8, 4, RAD>;
+    using P = Pipe3<8, 4, RAD, VEC>;
+    constexpr int NP = G::NP;
+    constexpr int NZ = 2 * RAD + 1;
+    constexpr int NR = kD3Rows + 2 * RAD;           // slab rows a thread reads
+    // waits for plane l at step l, as in the first form of the matrix kernel
+    // pipeline: loads of the NP-2 planes after it and the stores (one per
+    // output row of a thread) of the NP-1 steps since
+    constexpr int WL = (NP - 2) * P::D;
+    constexpr int WS = (NP - 2) * P::D + (NP - 1) * kD3Rows;
+    constexpr int STEADY = 2 * RAD + NP - 1;
+    __shared__ __attribute__((aligned(16))) char lds[NP * G::PLANE_BYTES];
+    __shared__ float wl[NZ * NZ * NZ];
+    const unsigned lds0 = lds_addr_of(lds);
+    const float *zf = static_cast<const float *>(p.zeros);
+
+    const int nxcd = p.nxcd;
+    const int nwg = gridDim.x;
+    const int xcd = blockIdx.x % nxcd;
+    const int stride = nwg / nxcd + (xcd < nwg % nxcd ? 1 : 0);
+    const int before = xcd * (nwg / nxcd) + min(xcd, nwg % nxcd);
+    const int range_begin = (int)((long long)p.total_items * before / nwg);
+    const int range_end = (int)((long long)p.total_items * (before + stride) / nwg);
+    const int first = range_begin + blockIdx.x / nxcd;
+    for (int i = threadIdx.x; i < NZ * NZ * NZ; i += kThreads) wl[i] = p.w[i];
+    // the copy's global loads are the only VMEM loads the compiler tracks
+    wait_vmcnt<0>();
+    __syncthreads();
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = threadIdx.x % kBandX;
+    const int y0 = (threadIdx.x / kBandX) * kD3Rows;
+    unsigned row_lds[P::DRW];
+#pragma unroll
+    for (int d = 0; d < P::DRW; ++d) row_lds[d] = min(wave + d * kWaves, G::SROWS - 1) * G::CPITCH * 4;
+
+#pragma unroll 1
+    for (int it = first; it < range_end; it += stride) {
+        int j = 0;
+        for (int t = 1; t < p.njobs; ++t) j += it >= p.job[t].item0 ? 1 : 0;
+        const MmaJob g = p.job[j];
+        const int nbands = (g.nx + kBandX - 1) / kBandX, nrb = (g.ny + G::WGH - 1) / G::WGH;
+        int local = it - g.item0;
+        const int X0 = __builtin_amdgcn_readfirstlane((local % nbands) * kBandX);
+        local /= nbands;
+        const int Y0 = __builtin_amdgcn_readfirstlane((local % nrb) * G::WGH);
+        const int z0 = __builtin_amdgcn_readfirstlane((local / nrb) * g.zc);
+        const int nzc = min(g.zc, g.nz - z0);
+        const int nload = nzc + 2 * RAD;
+        int row_off[P::DRW];
+#pragma unroll
+        for (int d = 0; d < P::DRW; ++d) {
+            const int gy = wrap<BC>(Y0 - RAD + min(wave + d * kWaves, G::SROWS - 1), g.ny);
+            row_off[d] = (BC != kBcZero || (gy >= 0 && gy < g.ny)) ? gy * g.nx : -1;
+        }
+        auto issue = [&](int l) {
+            const int zz = wrap<BC>(z0 - RAD + min(l, nload - 1), g.nz);
+            issue_plane<8, 4, RAD, VEC, BC>(g, zf, lds0 + (l % NP) * G::PLANE_BYTES, row_off, row_lds, X0, zz);
+        };
+#pragma unroll 1
+        for (int l = 0; l < NP - 1; ++l) issue(l);
+        const int rows_left = min(G::WGH, g.ny - Y0);
+        const int gx = X0 + c;
+        // output plane z0 + l - 2*RAD + i accumulates at step l in slot (i + l) % NZ
+        float acc[NZ][kD3Rows];
+#pragma unroll
+        for (int i = 0; i < NZ; ++i)
+#pragma unroll
+            for (int y = 0; y < kD3Rows; ++y) acc[i][y] = 0.f;
+        auto step = [&](auto rot, int l) {
+            constexpr int R = decltype(rot)::value;   // l % NZ
+            if (l < STEADY) wait_vmcnt<WL>();
+            else wait_vmcnt<WS>();
+            __builtin_amdgcn_s_barrier();
+            issue(l + NP - 1);
+            const float *sl = reinterpret_cast<const float *>(lds + (l % NP) * G::PLANE_BYTES);
+            // coefficients by LDS broadcast where they are used (the empty
+            // asm keeps the compiler from hoisting all of them)
+            int wbase = 0;
+            asm volatile("" : "+v"(wbase));
+            const float *w = wl + wbase;
+#pragma unroll
+            for (int dx = 0; dx < NZ; ++dx) {
+                int col = G::HL - RAD + c + dx;
+                asm volatile("" : "+v"(col));
+                float v[NR];
+#pragma unroll
+                for (int ry = 0; ry < NR; ++ry) v[ry] = sl[(y0 + ry) * G::CPITCH + col];
+                // input plane z0 - RAD + l is plane offset 2*RAD - i of
+                // logical output i
+#pragma unroll
+                for (int i = 0; i < NZ; ++i) {
+                    const int sidx = (i + R) % NZ, pz = 2 * RAD - i;
+#pragma unroll
+                    for (int dy = 0; dy < NZ; ++dy) {
+                        const float wc = w[(pz * NZ + dy) * NZ + dx];
+#pragma unroll
+                        for (int y = 0; y < kD3Rows; ++y) acc[sidx][y] = fmaf(wc, v[y + dy], acc[sidx][y]);
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < NZ; ++i)
+#pragma unroll
+                    for (int y = 0; y < kD3Rows; ++y) asm volatile("" : "+v"(acc[i][y]));
+            }
+            if (l >= 2 * RAD) {
+                float *out = static_cast<float *>(g.out) + ((size_t)(z0 + l - 2 * RAD) * g.ny + Y0) * g.nx;
+                const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
+#pragma unroll
+                for (int y = 0; y < kD3Rows; ++y) {
+                    const unsigned o = y0 + y < rows_left && gx < g.nx ? (unsigned)((y0 + y) * g.nx + gx) * 4u : kOob;
+                    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[R][y]), orsrc, o, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int y = 0; y < kD3Rows; ++y) acc[R][y] = 0.f;
+        };
+#pragma unroll 1
+        for (int l0 = 0; l0 < nload; l0 += NZ) unroll_steps<0, NZ>(step, l0, nload);
+        wait_vmcnt<0>();
+        __builtin_amdgcn_s_barrier();
+    }
+}
+
+template <int RAD, bool VEC, int BC>
+static hipError_t launch_lds3d_bc(const MmaArgs &a, int cus, int xcds, hipStream_t s) {
+    MmaArgs b = a;
+    b.nxcd = xcds;
+    const int g = a.total_items < cus ? a.total_items : cus;
+    hipLaunchKernelGGL((k_lds3d<RAD, VEC, BC>), dim3(g), dim3(kThreads), 0, s, b);
+    return hipGetLastError();
+}
+
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, bool VEC, int BC>
 static hipError_t launch3_bc(const MmaArgs &a, int cus, int xcds, hipStream_t s) {
     MmaArgs b = a;
@@ -379,6 +522,48 @@ bool mma3d_geometry(const MmaKey &k, int *wgh, int *row) {
             return true;
         }
     return false;
+}
+
+// Number a launch's work items as for the matrix kernels (z chunks so that
+// there is about one item per CU or more) and pick the variant.
+template <int RAD>
+static hipError_t launch_lds3d(MmaArgs &a, hipStream_t s) {
+    using G = Mma3Geom<8, 4, RAD>;
+    if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
+    int cus = 0, xcds = 0;
+    if (const hipError_t e = device_shape(&cus, &xcds); e != hipSuccess) return e;
+    int columns = 0;
+    for (int j = 0; j < a.njobs; ++j)
+        columns += ((a.job[j].nx + kBandX - 1) / kBandX) * ((a.job[j].ny + G::WGH - 1) / G::WGH);
+    const int chunks = columns >= cus ? 1 : (cus + columns - 1) / columns;
+    int items = 0;
+    bool vec = true, wrap1 = true;
+    for (int j = 0; j < a.njobs; ++j) {
+        MmaJob &g = a.job[j];
+        g.zc = (g.nz + chunks - 1) / chunks;
+        g.item0 = items;
+        items += ((g.nx + kBandX - 1) / kBandX) * ((g.ny + G::WGH - 1) / G::WGH) * ((g.nz + g.zc - 1) / g.zc);
+        vec = vec && (g.nx & 3) == 0;
+        wrap1 = wrap1 && g.ny >= G::SROWS && g.nx >= kBandX + 2 * RAD && g.nz >= 2 * RAD + 1;
+    }
+    a.total_items = items;
+    if (items == 0) return hipSuccess;
+    if (vec) {
+        if (!a.periodic) return launch_lds3d_bc<RAD, true, kBcZero>(a, cus, xcds, s);
+        if (wrap1) return launch_lds3d_bc<RAD, true, kBcWrap1>(a, cus, xcds, s);
+        return launch_lds3d_bc<RAD, true, kBcWrapN>(a, cus, xcds, s);
+    }
+    if (!a.periodic) return launch_lds3d_bc<RAD, false, kBcZero>(a, cus, xcds, s);
+    if (wrap1) return launch_lds3d_bc<RAD, false, kBcWrap1>(a, cus, xcds, s);
+    return launch_lds3d_bc<RAD, false, kBcWrapN>(a, cus, xcds, s);
+}
+
+MmaLaunch find_lds_direct3d(int rad) {
+    switch (rad) {
+        case 1: return &launch_lds3d<1>;
+        case 2: return &launch_lds3d<2>;
+    }
+    return nullptr;
 }
 
 int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max) {

@@ -465,12 +465,14 @@ ss_status plan_mma2d_f64(ss_plan_ *p) {
 
 ss_status plan_direct(ss_plan_ *p) {
     const bool f64 = p->dtype == SS_F64;
-    // 2-D FP32-state or plane grids run on the LDS-pipelined kernel (planes
-    // need rows of a multiple of 8 values); FP64, 1-D and 3-D on the plain one
+    // 2-D FP32-state or plane grids and 3-D FP32-state grids run on the
+    // LDS-pipelined kernels (planes need rows of a multiple of 8 values);
+    // FP64, 1-D and the rest on the plain one
     const int state = mma_state(p->dtype);
     MmaLaunch lds = nullptr;
     if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0) && slab_offsets_fit(p))
         lds = find_lds_direct2d(p->rad, state);
+    if (!f64 && p->ndim == 3 && state == kStateF32 && slab_offsets_fit(p)) lds = find_lds_direct3d(p->rad);
     const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
     const size_t o_zero = (wbytes + 255) & ~(size_t)255;
     std::vector<uint8_t> blob(o_zero + 1024, 0);
