@@ -24,8 +24,6 @@ struct DPipe {
     static constexpr int W = (G::NSLAB - 2) * D + (S < G::NSLAB - 1 ? S : G::NSLAB - 1) * M;
 };
 
-__device__ inline float bf16_value(unsigned short b) { return __uint_as_float((unsigned)b << 16); }
-
 template <int RAD, int STATE, bool VEC>
 __device__ inline void direct_item(const MmaJob &g, const float *wl, const char *slab, int X0, int Y0) {
     using G = MmaGeom<8, 8, RAD, STATE>;
@@ -57,13 +55,8 @@ __device__ inline void direct_item(const MmaJob &g, const float *wl, const char 
         float v[kRowsPerThread + 2 * RAD];
 #pragma unroll
         for (int ry = 0; ry < kRowsPerThread + 2 * RAD; ++ry) {
-            if constexpr (STATE == kStatePlanes) {
-                const unsigned short *s16 = reinterpret_cast<const unsigned short *>(slab);
-                v[ry] = bf16_value(s16[planes_index<G::RBD>(y0 + ry, col, 0)]) +
-                        bf16_value(s16[planes_index<G::RBD>(y0 + ry, col, 1)]);
-            } else {
-                v[ry] = reinterpret_cast<const float *>(slab)[(y0 + ry) * G::CPITCH + col];
-            }
+            // planes slabs hold FP32 values by now (planes_to_f32)
+            v[ry] = reinterpret_cast<const float *>(slab)[(y0 + ry) * (STATE == kStatePlanes ? G::RBD : G::CPITCH) + col];
         }
 #pragma unroll
         for (int dy = 0; dy < K; ++dy) {
@@ -97,6 +90,22 @@ __device__ inline void direct_item(const MmaJob &g, const float *wl, const char 
             const unsigned o = y0 + y < rows_left && gx < g.nx ? (unsigned)((y0 + y) * g.nx + gx) * 4u : kOob;
             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[y]), r, o, 0, 0);
         }
+    }
+}
+
+// Planes slab rows hold hi and lo dword pairs: (hi, lo) of values 2m, 2m+1
+// at dwords 2m, 2m+1.  Replacing each pair by the two FP32 values hi + lo
+// (exact in FP32) leaves value column c at dword c: an FP32 slab of row pitch
+// RBD, which the direct computation reads once per use.
+template <int RAD>
+__device__ inline void planes_to_f32(char *slab) {
+    using G = MmaGeom<8, 8, RAD, kStatePlanes>;
+    constexpr int PAIRS = (2 * G::HLB + kBandX) / 2;   // dword pairs a row holds
+    for (int e = threadIdx.x; e < G::SROWS * PAIRS; e += kThreads) {
+        unsigned *w = reinterpret_cast<unsigned *>(slab) + (e / PAIRS) * G::RBD + 2 * (e % PAIRS);
+        const unsigned hi = w[0], lo = w[1];
+        w[0] = __float_as_uint(__uint_as_float(hi << 16) + __uint_as_float(lo << 16));
+        w[1] = __float_as_uint(__uint_as_float(hi & 0xffff0000u) + __uint_as_float(lo & 0xffff0000u));
     }
 }
 
@@ -152,6 +161,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds2d(MmaArgs p) {
         if constexpr (G::NHALO > 0) {
             put_halo<8, 8, RAD, STATE>(slab(cur), strip(cur));
             __builtin_amdgcn_s_waitcnt(0xC07F);
+            __builtin_amdgcn_s_barrier();
+        }
+        if constexpr (STATE == kStatePlanes) {
+            planes_to_f32<RAD>(slab(cur));
+            __builtin_amdgcn_s_waitcnt(0xC07F);      // lgkmcnt(0): converted values written
             __builtin_amdgcn_s_barrier();
         }
         issue(s + NS - 1);

@@ -73,13 +73,6 @@ struct MmaGeom {
     static_assert(NSLAB * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes, "slabs exceed LDS");
 };
 
-// Element index (16-bit units) of value column col of plane pl in planes
-// slab row r.
-template <int RBD>
-__host__ __device__ constexpr int planes_index(int r, int col, int pl) {
-    return 2 * (r * RBD + (col & ~1) + pl) + (col & 1);
-}
-
 // 3-D kernel: a work item is a column of the grid (a 256-column band of
 // WGH rows) over a range of z planes; the workgroup marches through z with a
 // ring of NP plane slabs in LDS, each output plane using the 2*RAD+1 input
