@@ -128,6 +128,71 @@ static hipError_t launch_r(DirectArgs &a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// Band points of an ny x nx grid within b of an edge: rows 0..b-1, rows
+// ny-b..ny-1, then columns 0..b-1 and nx-b..nx-1 of the rows between (the
+// whole grid when it is narrower than 2b).
+__host__ __device__ inline int band_points(int ny, int nx, int b) {
+    if (ny <= 2 * b || nx <= 2 * b) return ny * nx;
+    return 2 * b * nx + 2 * b * (ny - 2 * b);
+}
+
+// Exact value of two zero-halo sweeps at band point i of a grid:
+// y2(p) = sum_a w[a] [p+a in grid] sum_b w[b] x[p+a+b] [p+a+b in grid]
+// (correlation, offsets -r..r), in FP64.  The fused launch computed the
+// composed stencil on the zero-padded grid, which differs exactly where p+a
+// leaves the grid, i.e. within r of an edge.
+__global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.total) return;
+    int j = 0;
+    for (int t = 1; t < a.njobs; ++t) j += idx >= a.job[t].point0 ? 1 : 0;
+    const EdgeJob &g = a.job[j];
+    const int b = a.rad, k = 2 * a.rad + 1;
+    int l = idx - g.point0, y, x;
+    if (g.ny <= 2 * b || g.nx <= 2 * b) {
+        y = l / g.nx;
+        x = l % g.nx;
+    } else if (l < 2 * b * g.nx) {
+        const int r = l / g.nx;
+        y = r < b ? r : g.ny - 2 * b + r;
+        x = l % g.nx;
+    } else {
+        l -= 2 * b * g.nx;
+        const int r = l / (2 * b), c = l % (2 * b);
+        y = b + r;
+        x = c < b ? c : g.nx - 2 * b + c;
+    }
+    double acc = 0.0;
+    for (int ay = -b; ay <= b; ++ay)
+        for (int ax = -b; ax <= b; ++ax) {
+            const int qy = y + ay, qx = x + ax;
+            if (qy < 0 || qy >= g.ny || qx < 0 || qx >= g.nx) continue;
+            double inner = 0.0;
+            for (int by = -b; by <= b; ++by)
+                for (int bx = -b; bx <= b; ++bx) {
+                    const int sy = qy + by, sx = qx + bx;
+                    if (sy < 0 || sy >= g.ny || sx < 0 || sx >= g.nx) continue;
+                    inner += a.w[(by + b) * k + (bx + b)] * (double)g.in[(size_t)sy * g.nx + sx];
+                }
+            acc += a.w[(ay + b) * k + (ax + b)] * inner;
+        }
+    g.out[(size_t)y * g.nx + x] = (float)acc;
+}
+
+hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s) {
+    if (a.njobs < 1 || a.njobs > kMaxJobs || a.rad < 1) return hipErrorInvalidValue;
+    long long total = 0;
+    for (int j = 0; j < a.njobs; ++j) {
+        a.job[j].point0 = (int)total;
+        total += band_points(a.job[j].ny, a.job[j].nx, a.rad);
+    }
+    if (total > (1ll << 31) - 256) return hipErrorInvalidValue;
+    a.total = (int)total;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge2d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s) {
     if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
     switch (kind) {

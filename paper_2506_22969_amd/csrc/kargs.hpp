@@ -46,6 +46,23 @@ struct DirectJob {
     int block0;
 };
 
+// Edge correction of a two-sweep fused launch on a 2-D zero-halo grid: the
+// points within r of an edge get the exact two-sweep value.
+struct EdgeJob {
+    const float *in;   // state the fused launch read
+    float *out;        // the fused launch's output (band points overwritten)
+    int ny, nx;
+    int point0;        // first band point of this grid in the launch
+};
+struct EdgeArgs {
+    int njobs;
+    int total;
+    EdgeJob job[kMaxJobs];
+    int rad;
+    const double *w;   // the unfused (2r+1)^2 coefficients
+};
+hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s);
+
 // Direct sweep: one (2r+1)^3 box (r = 0 on missing axes).
 struct DirectArgs {
     int njobs;

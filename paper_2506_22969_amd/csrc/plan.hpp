@@ -32,6 +32,11 @@ struct ss_plan_ {
     bool host_only = false;
     uint64_t klass = 0;               // equal for plans with identical device tables
     ss_plan_ *rem = nullptr;          // unfused plan for leftover sweeps
+    // two fused sweeps on a 2-D zero-halo grid: the band within edge_rad of
+    // an edge is recomputed exactly from the unfused coefficients
+    std::vector<double> w1;           // unfused coefficients
+    int edge_rad = 0;
+    double *edge_w = nullptr;         // device copy of w1
 };
 
 namespace ss {

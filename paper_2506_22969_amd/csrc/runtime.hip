@@ -507,6 +507,7 @@ void free_plan(ss_plan_ *p) {
     if (!p) return;
     free_plan(p->rem);
     if (p->dev) (void)hipFree(p->dev);
+    if (p->edge_w) (void)hipFree(p->edge_w);
     delete p;
 }
 
@@ -525,7 +526,11 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     if (o.fuse_steps < 1 || o.fuse_steps > 8) return SS_E_INVALID;
     if (o.engine < SS_ENGINE_AUTO || o.engine > SS_ENGINE_DIRECT) return SS_E_INVALID;
     if ((o.r1 == 0) != (o.r2 == 0) || o.r1 < 0 || o.r2 < 0) return SS_E_INVALID;
-    if (o.fuse_steps > 1 && o.boundary != SS_BC_PERIODIC) return SS_E_UNSUPPORTED;
+    // a zero halo fuses two 2-D sweeps of an FP32 state, with the edge band
+    // recomputed (the composed stencil is exact only away from the edges)
+    const bool edge_fused = o.fuse_steps > 1 && o.boundary == SS_BC_ZERO;
+    if (edge_fused && (o.fuse_steps != 2 || ndim != 2 || (dtype != SS_F32_SPLIT_F16 && dtype != SS_F32_SPLIT_BF16)))
+        return SS_E_UNSUPPORTED;
     if (o.fuse_steps > 1 && !allow_fuse) return SS_E_INVALID;
     if (o.flags & ~SS_FLAG_HOST_ONLY) return SS_E_INVALID;
 
@@ -559,6 +564,10 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     }
     int kf = k0;
     p->w = o.fuse_steps > 1 ? compose(w, ndim, k0, o.fuse_steps, &kf) : w;
+    if (edge_fused) {
+        p->w1 = w;
+        p->edge_rad = radius;
+    }
     p->k = kf;
     p->rad = (kf - 1) / 2;
     // a periodic grid must be at least as wide as the composed stencil
@@ -595,6 +604,17 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
         free_plan(p);
         return st;
     }
+    if (edge_fused && !p->host_only) {
+        if (hipMalloc(&p->edge_w, p->w1.size() * sizeof(double)) != hipSuccess) {
+            p->edge_w = nullptr;
+            free_plan(p);
+            return SS_E_NOMEM;
+        }
+        if (hipMemcpy(p->edge_w, p->w1.data(), p->w1.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            free_plan(p);
+            return SS_E_DEVICE;
+        }
+    }
     if (o.fuse_steps > 1) {
         ss_plan_opts ro = o;
         ro.fuse_steps = 1;
@@ -614,7 +634,7 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     inf.engine = p->engine;
     inf.dtype = dtype;
     inf.boundary = p->boundary;
-    inf.launches_per_sweep = 1;
+    inf.launches_per_sweep = p->edge_rad ? 2 : 1;
     for (int d = 0; d < 3; ++d) inf.dims[d] = p->dims[d];
     // plans with the same class share device-table contents: their grids can
     // be swept by one launch
@@ -626,6 +646,7 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     const int32_t key[8] = {p->engine, p->dtype, p->boundary, p->k, inf.r1, inf.r2, ndim, p->fuse};
     mix(key, sizeof key);
     mix(p->w.data(), p->w.size() * sizeof(double));
+    mix(p->w1.data(), p->w1.size() * sizeof(double));
     p->klass = h;
     inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
@@ -654,19 +675,31 @@ namespace ss {
 hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
                        const int64_t (*dims)[3], hipStream_t s) {
     if (n < 1 || n > kMaxJobs) return hipErrorInvalidValue;
+    hipError_t e;
     if (!p->mma) {
         DirectArgs a = p->dargs;
         a.njobs = n;
         for (int j = 0; j < n; ++j)
             a.job[j] = DirectJob{in[j], out[j], (int)dims[j][0], (int)dims[j][1], (int)dims[j][2], 0};
         const int kind = p->dtype == SS_F64 ? kDirectF64 : p->dtype == SS_SPLIT_BF16 ? kDirectPlanes : kDirectF32;
-        return launch_direct(a, kind, s);
+        e = launch_direct(a, kind, s);
+    } else {
+        MmaArgs a = p->margs;
+        a.njobs = n;
+        for (int j = 0; j < n; ++j)
+            a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
+        e = p->mma(a, s);
     }
-    MmaArgs a = p->margs;
-    a.njobs = n;
+    // zero-halo fused sweeps: exact values for the band along the edges
+    if (e != hipSuccess || !p->edge_w) return e;
+    EdgeArgs ea{};
+    ea.njobs = n;
+    ea.rad = p->edge_rad;
+    ea.w = p->edge_w;
     for (int j = 0; j < n; ++j)
-        a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
-    return p->mma(a, s);
+        ea.job[j] = EdgeJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],
+                            (int)dims[j][2], 0};
+    return launch_edge2d(ea, s);
 }
 
 hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {
@@ -680,7 +713,7 @@ size_t plan_state_bytes(const ss_plan_ *p) { return state_bytes(p->dtype); }
 bool same_class(const ss_plan_ *a, const ss_plan_ *b) {
     return a->klass == b->klass && a->engine == b->engine && a->dtype == b->dtype &&
            a->boundary == b->boundary && a->k == b->k && a->ndim == b->ndim && a->fuse == b->fuse &&
-           a->info.r1 == b->info.r1 && a->info.r2 == b->info.r2 && a->w == b->w;
+           a->info.r1 == b->info.r1 && a->info.r2 == b->info.r2 && a->w == b->w && a->w1 == b->w1;
 }
 
 }  // namespace ss

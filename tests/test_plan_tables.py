@@ -182,3 +182,19 @@ def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
     assert np.array_equal(got, np.array(ref, dtype=np.int32))
     if shape == "star" and radius == 3:
         assert len(ref) < (len(T.group(T.plane_pairs(d)[0], 64)) if engine == "smfmac" else -(-d.k_prime // 32) * 32)
+
+
+def test_zero_halo_fusion_scope():
+    """Two fused sweeps with a zero halo: 2-D FP32-state plans only (the band
+    along the edges is a second launch); planes, 3-D and S = 3 stay
+    unsupported."""
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
+    with native.Plan("box", 1, w, (64, 64), "f32_split_bf16", fuse_steps=2, host_only=True) as p:
+        info = p.info
+        assert info["fuse_steps"] == 2 and info["k"] == 5 and info["launches_per_sweep"] == 2
+    for dims, dtype, fuse in [((64, 64), "split_bf16", 2), ((64, 64), "f32_split_f16", 3)]:
+        with pytest.raises(native.SparStencilError):
+            native.Plan("box", 1, w, dims, dtype, fuse_steps=fuse, host_only=True)
+    w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 1, w3, (8, 8, 8), "f32_split_f16", fuse_steps=2, host_only=True)
