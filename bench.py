@@ -2,10 +2,13 @@
 binary16 hi+lo split products on gfx950 sparse MFMA (SMFMAC).
 
 One step = one sparstencil_run of the whole workload (100 sweeps) on grids
-already resident in HBM.  Prints one JSON line with GStencil/s (paper
-Section 4.1, Eq. 12: T * prod(N_i) / (t * 1e9)), latency percentiles, the
-dense-MFMA and direct-FMA engines on the same workload, the roofline of the
-sparse sweep kernel (HIP events on its stream) and the CPU oracle baseline.
+already resident in HBM; by default two sweeps are fused per launch (the
+composed stencil, with the band within r of the edges recomputed exactly by
+a second, small launch), as the paper fuses sweeps.  Prints one JSON line
+with GStencil/s (paper Section 4.1, Eq. 12: T * prod(N_i) / (t * 1e9)),
+latency percentiles, the dense-MFMA and direct-FMA engines on the same
+workload (fused and unfused), the roofline of the sparse sweep launch (HIP
+events on its stream) and the CPU oracle baseline.
 """
 from __future__ import annotations
 
@@ -38,6 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--engines", default="smfmac,mfma,direct",
                     help="engines to time; the first is the headline")
+    ap.add_argument("--fuse", type=int, default=2, choices=[1, 2],
+                    help="sweeps fused per launch on the headline workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep-loop", type=int, default=40, help="sweeps timed for the roofline")
@@ -60,20 +65,21 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_entry():
-    """Measured HBM bytes per launch, only if taken on the current kernel."""
+def traffic_entry(fuse: int):
+    """Measured HBM bytes per launch, only if taken on the current kernel and
+    fusion."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash():
+    if t.get("kernel_sha256_16") != kernel_hash() or t.get("fuse_steps", 1) != fuse:
         return None
     return t.get("bytes_per_launch")
 
 
-def time_engine(native, torch, w, x0_dev, engine, steps, warmup, stream):
-    plan = native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine=engine)
+def time_engine(native, torch, w, x0_dev, engine, steps, warmup, stream, fuse):
+    plan = native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine=engine, fuse_steps=fuse)
     info = plan.info
     a = torch.empty_like(x0_dev)
     b = torch.empty_like(x0_dev)
@@ -353,7 +359,7 @@ def serving_leg(native, torch, n_jobs: int, load: float):
     }
 
 
-def profile_only(name: str):
+def profile_only(name: str, fuse: int):
     """One grid copy and four sweeps of one workload on the sparse engine,
     nothing else: a short program for counter collection."""
     import torch
@@ -365,7 +371,7 @@ def profile_only(name: str):
     if name == "box2d9p":
         w = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(NY, NX))[0]
         x = torch.from_numpy(synthetic.grid_f32((NY, NX), seed=0)).to("cuda:0")
-        plan = native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac")
+        plan = native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac", fuse_steps=fuse)
     elif name == "box2d49p_planes":
         w = synthetic.random_coeffs("box", 3, 2, seed=277, grid_shape=(8192, 8192))[0]
         bits = synthetic.grid_bf16_planes((8192, 8192), seed=0)
@@ -396,7 +402,7 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.profile:
-        profile_only(args.profile)
+        profile_only(args.profile, args.fuse)
         return
     import torch
 
@@ -413,17 +419,27 @@ def main():
     engines = [e for e in args.engines.split(",") if e]
     results = {}
     head = None
+    unfused = {}
     for i, eng in enumerate(engines):
         steps = args.steps if i == 0 else max(2, args.steps // 3)
-        plan, info, lat, t_total, out = time_engine(native, torch, w, x0_dev, eng, steps, args.warmup, stream)
+        plan, info, lat, t_total, out = time_engine(native, torch, w, x0_dev, eng, steps, args.warmup, stream,
+                                                    args.fuse)
         gst = SWEEPS * NY * NX / (t_total / steps) / 1e9
         results[eng] = {"gstencil_s": round(gst, 2), "ms_per_run": round(t_total / steps * 1e3, 3),
                         "tile": [info["r1"], info["r2"]], "k_pad": info["k_pad"],
-                        "plan_ms": round(info["plan_seconds"] * 1e3, 3)}
+                        "fuse_steps": info["fuse_steps"], "plan_ms": round(info["plan_seconds"] * 1e3, 3)}
         if i == 0:
             head = (plan, info, lat, t_total, steps, out.cpu().numpy())
         else:
             plan.close()
+        if args.fuse > 1:
+            # the same engine one sweep per launch, for comparison
+            p1, i1, _, t1, _ = time_engine(native, torch, w, x0_dev, eng, max(2, args.steps // 3), 1, stream, 1)
+            unfused[eng] = {"gstencil_s": round(SWEEPS * NY * NX / (t1 / max(2, args.steps // 3)) / 1e9, 2),
+                            "tile": [i1["r1"], i1["r2"]], "k_pad": i1["k_pad"]}
+            if i == 0:
+                unfused[eng]["sweep_ms"] = round(sweep_roofline(torch, p1, x0_dev, stream, args.sweep_loop), 4)
+            p1.close()
         sys.stdout.flush()
     plan, info, lat, t_total, steps, gpu_out = head
     ms = t_total / steps * 1e3
@@ -433,9 +449,13 @@ def main():
     alg_bytes = BYTES_PER_POINT * NY * NX
     achieved = alg_bytes / (sweep_ms / 1e3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(),
-            "kernel": "k_mma2d (sparse, binary16 split)", "sweep_ms": round(sweep_ms, 4),
-            "algorithmic_bytes_per_launch": alg_bytes}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(args.fuse),
+            "kernel": "k_mma2d (sparse, binary16 split)" +
+                      (f", {args.fuse} sweeps per launch, plus the edge-band launch" if args.fuse > 1 else ""),
+            "sweep_ms": round(sweep_ms, 4), "algorithmic_bytes_per_launch": alg_bytes}
+    if unfused.get(engines[0], {}).get("sweep_ms"):
+        u_ms = unfused[engines[0]]["sweep_ms"]
+        unfused[engines[0]]["roofline_frac"] = round(alg_bytes / (u_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     plan.close()
 
     line = {
@@ -445,11 +465,13 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f16", "data": "synthetic",
         "config": {"workload": "Box-2D9P 10240x10240 FP32 state, binary16 hi+lo split products "
                                "with FP32 accumulation, 100 sweeps, zero halo",
-                   "engine": engines[0], "tile": [info["r1"], info["r2"]], "k_pad": info["k_pad"],
+                   "engine": engines[0], "fuse_steps": info["fuse_steps"],
+                   "tile": [info["r1"], info["r2"]], "k_pad": info["k_pad"],
                    "coeff_seed": cseed, "grid_seed": 0, "accumulate": "f32"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},
         "engines": results,
+        "engines_unfused": unfused,
         "roofline": roof,
     }
     del x0_dev

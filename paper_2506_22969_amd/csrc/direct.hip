@@ -140,14 +140,17 @@ __host__ __device__ inline int band_points(int ny, int nx, int b) {
 // y2(p) = sum_a w[a] [p+a in grid] sum_b w[b] x[p+a+b] [p+a+b in grid]
 // (correlation, offsets -r..r), in FP64.  The fused launch computed the
 // composed stencil on the zero-padded grid, which differs exactly where p+a
-// leaves the grid, i.e. within r of an edge.
+// leaves the grid, i.e. within r of an edge.  R > 0: the (4R+1)^2 inputs
+// around p are loaded once into registers (zero outside the grid); R = 0:
+// any radius, straight from memory.
+template <int R>
 __global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
     const int idx = blockIdx.x * 256 + threadIdx.x;
     if (idx >= a.total) return;
     int j = 0;
     for (int t = 1; t < a.njobs; ++t) j += idx >= a.job[t].point0 ? 1 : 0;
     const EdgeJob &g = a.job[j];
-    const int b = a.rad, k = 2 * a.rad + 1;
+    const int b = R > 0 ? R : a.rad, k = 2 * b + 1;
     int l = idx - g.point0, y, x;
     if (g.ny <= 2 * b || g.nx <= 2 * b) {
         y = l / g.nx;
@@ -163,19 +166,44 @@ __global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
         x = c < b ? c : g.nx - 2 * b + c;
     }
     double acc = 0.0;
-    for (int ay = -b; ay <= b; ++ay)
-        for (int ax = -b; ax <= b; ++ax) {
-            const int qy = y + ay, qx = x + ax;
-            if (qy < 0 || qy >= g.ny || qx < 0 || qx >= g.nx) continue;
-            double inner = 0.0;
-            for (int by = -b; by <= b; ++by)
-                for (int bx = -b; bx <= b; ++bx) {
-                    const int sy = qy + by, sx = qx + bx;
-                    if (sy < 0 || sy >= g.ny || sx < 0 || sx >= g.nx) continue;
-                    inner += a.w[(by + b) * k + (bx + b)] * (double)g.in[(size_t)sy * g.nx + sx];
-                }
-            acc += a.w[(ay + b) * k + (ax + b)] * inner;
-        }
+    if constexpr (R > 0) {
+        constexpr int E = 4 * R + 1;
+        float xs[E][E];
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                const int sy = y - 2 * R + i, sx = x - 2 * R + c;
+                xs[i][c] = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? g.in[(size_t)sy * g.nx + sx] : 0.f;
+            }
+#pragma unroll
+        for (int ay = -R; ay <= R; ++ay)
+#pragma unroll
+            for (int ax = -R; ax <= R; ++ax) {
+                if (y + ay < 0 || y + ay >= g.ny || x + ax < 0 || x + ax >= g.nx) continue;
+                double inner = 0.0;
+#pragma unroll
+                for (int by = -R; by <= R; ++by)
+#pragma unroll
+                    for (int bx = -R; bx <= R; ++bx)
+                        inner += a.w[(by + R) * k + (bx + R)] * (double)xs[2 * R + ay + by][2 * R + ax + bx];
+                acc += a.w[(ay + R) * k + (ax + R)] * inner;
+            }
+    } else {
+        for (int ay = -b; ay <= b; ++ay)
+            for (int ax = -b; ax <= b; ++ax) {
+                const int qy = y + ay, qx = x + ax;
+                if (qy < 0 || qy >= g.ny || qx < 0 || qx >= g.nx) continue;
+                double inner = 0.0;
+                for (int by = -b; by <= b; ++by)
+                    for (int bx = -b; bx <= b; ++bx) {
+                        const int sy = qy + by, sx = qx + bx;
+                        if (sy < 0 || sy >= g.ny || sx < 0 || sx >= g.nx) continue;
+                        inner += a.w[(by + b) * k + (bx + b)] * (double)g.in[(size_t)sy * g.nx + sx];
+                    }
+                acc += a.w[(ay + b) * k + (ax + b)] * inner;
+            }
+    }
     g.out[(size_t)y * g.nx + x] = (float)acc;
 }
 
@@ -189,7 +217,9 @@ hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s) {
     if (total > (1ll << 31) - 256) return hipErrorInvalidValue;
     a.total = (int)total;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge2d, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a);
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (a.rad == 1) hipLaunchKernelGGL(k_edge2d<1>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_edge2d<0>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
