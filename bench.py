@@ -2,9 +2,9 @@
 binary16 hi+lo split products on gfx950 sparse MFMA (SMFMAC).
 
 One step = one sparstencil_run of the whole workload (100 sweeps) on grids
-already resident in HBM; by default two sweeps are fused per launch (the
-composed stencil, with the band within r of the edges recomputed exactly by
-a second, small launch), as the paper fuses sweeps.  Prints one JSON line
+already resident in HBM; by default three sweeps are fused per launch (the
+composed stencil, with the band within 2r of the edges recomputed exactly by
+a second, small launch), as the paper fuses three sweeps.  Prints one JSON line
 with GStencil/s (paper Section 4.1, Eq. 12: T * prod(N_i) / (t * 1e9)),
 latency percentiles, the dense-MFMA and direct-FMA engines on the same
 workload (fused and unfused), the roofline of the sparse sweep launch (HIP
@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--engines", default="smfmac,mfma,direct",
                     help="engines to time; the first is the headline")
-    ap.add_argument("--fuse", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--fuse", type=int, default=3, choices=[1, 2, 3],
                     help="sweeps fused per launch on the headline workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)

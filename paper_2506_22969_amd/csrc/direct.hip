@@ -136,60 +136,94 @@ __host__ __device__ inline int band_points(int ny, int nx, int b) {
     return 2 * b * nx + 2 * b * (ny - 2 * b);
 }
 
-// Exact value of two zero-halo sweeps at band point i of a grid:
-// y2(p) = sum_a w[a] [p+a in grid] sum_b w[b] x[p+a+b] [p+a+b in grid]
-// (correlation, offsets -r..r), in FP64.  The fused launch computed the
-// composed stencil on the zero-padded grid, which differs exactly where p+a
-// leaves the grid, i.e. within r of an edge.  R > 0: the (4R+1)^2 inputs
-// around p are loaded once into registers (zero outside the grid); R = 0:
-// any radius, straight from memory.
-template <int R>
-__global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
-    const int idx = blockIdx.x * 256 + threadIdx.x;
-    if (idx >= a.total) return;
+// Band point i of a launch -> its grid and (y, x), band width b.
+__device__ inline const EdgeJob &band_point(const EdgeArgs &a, int idx, int b, int *py, int *px) {
     int j = 0;
     for (int t = 1; t < a.njobs; ++t) j += idx >= a.job[t].point0 ? 1 : 0;
     const EdgeJob &g = a.job[j];
-    const int b = R > 0 ? R : a.rad, k = 2 * b + 1;
-    int l = idx - g.point0, y, x;
+    int l = idx - g.point0;
     if (g.ny <= 2 * b || g.nx <= 2 * b) {
-        y = l / g.nx;
-        x = l % g.nx;
+        *py = l / g.nx;
+        *px = l % g.nx;
     } else if (l < 2 * b * g.nx) {
         const int r = l / g.nx;
-        y = r < b ? r : g.ny - 2 * b + r;
-        x = l % g.nx;
+        *py = r < b ? r : g.ny - 2 * b + r;
+        *px = l % g.nx;
     } else {
         l -= 2 * b * g.nx;
         const int r = l / (2 * b), c = l % (2 * b);
-        y = b + r;
-        x = c < b ? c : g.nx - 2 * b + c;
+        *py = b + r;
+        *px = c < b ? c : g.nx - 2 * b + c;
     }
-    double acc = 0.0;
+    return g;
+}
+
+// Exact value of S zero-halo sweeps at a band point p: y_s = W y_{s-1} with
+// every intermediate state zero outside the grid (correlation, offsets
+// -r..r), in FP64.  The fused launch applied the composed stencil to the
+// zero-padded grid, which differs exactly where an intermediate point p+a
+// leaves the grid, i.e. within r(S-1) of an edge.  R > 0: the inputs within
+// RS of p are loaded once into registers and each sweep is evaluated on the
+// shrinking square of points it still feeds; R = 0 (two sweeps of any
+// radius): straight from memory.
+template <int R, int S>
+__global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.total) return;
+    const int b = R > 0 ? R * (S - 1) : a.rad;
+    int y, x;
+    const EdgeJob &g = band_point(a, idx, b, &y, &x);
+    double result = 0.0;
     if constexpr (R > 0) {
-        constexpr int E = 4 * R + 1;
-        float xs[E][E];
+        constexpr int K = 2 * R + 1;
+        constexpr int H = R * S;            // half width of the input square
+        constexpr int E = 2 * H + 1;
+        double cur[E][E];
 #pragma unroll
         for (int i = 0; i < E; ++i)
 #pragma unroll
             for (int c = 0; c < E; ++c) {
-                const int sy = y - 2 * R + i, sx = x - 2 * R + c;
-                xs[i][c] = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? g.in[(size_t)sy * g.nx + sx] : 0.f;
+                const int sy = y - H + i, sx = x - H + c;
+                cur[i][c] = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? (double)g.in[(size_t)sy * g.nx + sx] : 0.0;
             }
+        double w[K][K];
 #pragma unroll
-        for (int ay = -R; ay <= R; ++ay)
+        for (int i = 0; i < K; ++i)
 #pragma unroll
-            for (int ax = -R; ax <= R; ++ax) {
-                if (y + ay < 0 || y + ay >= g.ny || x + ax < 0 || x + ax >= g.nx) continue;
-                double inner = 0.0;
+            for (int c = 0; c < K; ++c) w[i][c] = a.w[i * K + c];
+        // sweep s maps the square of half width H - (s-1)R to H - sR
 #pragma unroll
-                for (int by = -R; by <= R; ++by)
+        for (int s = 1; s <= S; ++s) {
+            const int h = H - s * R;        // half width after sweep s
 #pragma unroll
-                    for (int bx = -R; bx <= R; ++bx)
-                        inner += a.w[(by + R) * k + (bx + R)] * (double)xs[2 * R + ay + by][2 * R + ax + bx];
-                acc += a.w[(ay + R) * k + (ax + R)] * inner;
-            }
+            for (int i = 0; i < E; ++i)
+#pragma unroll
+                for (int c = 0; c < E; ++c) {
+                    if (i < H - h || i > H + h || c < H - h || c > H + h) continue;
+                    const int sy = y - H + i, sx = x - H + c;
+                    double v = 0.0;
+                    if (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) {
+#pragma unroll
+                        for (int dy = 0; dy < K; ++dy)
+#pragma unroll
+                            for (int dx = 0; dx < K; ++dx) v += w[dy][dx] * cur[i - R + dy][c - R + dx];
+                    }
+                    // written in place from the outside in is unsafe, so
+                    // results of this sweep go to the corner block first
+                    cur[i - (H - h)][c - (H - h)] = v;
+                }
+            // move the new square (stored at the top-left) back to the centre
+#pragma unroll
+            for (int i = E - 1; i >= 0; --i)
+#pragma unroll
+                for (int c = E - 1; c >= 0; --c) {
+                    if (i < H - h || i > H + h || c < H - h || c > H + h) continue;
+                    cur[i][c] = cur[i - (H - h)][c - (H - h)];
+                }
+        }
+        result = cur[H][H];
     } else {
+        const int k = 2 * b + 1;
         for (int ay = -b; ay <= b; ++ay)
             for (int ax = -b; ax <= b; ++ax) {
                 const int qy = y + ay, qx = x + ax;
@@ -201,25 +235,28 @@ __global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
                         if (sy < 0 || sy >= g.ny || sx < 0 || sx >= g.nx) continue;
                         inner += a.w[(by + b) * k + (bx + b)] * (double)g.in[(size_t)sy * g.nx + sx];
                     }
-                acc += a.w[(ay + b) * k + (ax + b)] * inner;
+                result += a.w[(ay + b) * k + (ax + b)] * inner;
             }
     }
-    g.out[(size_t)y * g.nx + x] = (float)acc;
+    g.out[(size_t)y * g.nx + x] = (float)result;
 }
 
 hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s) {
-    if (a.njobs < 1 || a.njobs > kMaxJobs || a.rad < 1) return hipErrorInvalidValue;
+    if (a.njobs < 1 || a.njobs > kMaxJobs || a.rad < 1 || a.steps < 2 || a.steps > 3) return hipErrorInvalidValue;
+    if (a.steps == 3 && a.rad != 1) return hipErrorInvalidValue;
+    const int b = a.rad * (a.steps - 1);
     long long total = 0;
     for (int j = 0; j < a.njobs; ++j) {
         a.job[j].point0 = (int)total;
-        total += band_points(a.job[j].ny, a.job[j].nx, a.rad);
+        total += band_points(a.job[j].ny, a.job[j].nx, b);
     }
     if (total > (1ll << 31) - 256) return hipErrorInvalidValue;
     a.total = (int)total;
     if (total == 0) return hipSuccess;
     const dim3 grid((unsigned)((total + 255) / 256));
-    if (a.rad == 1) hipLaunchKernelGGL(k_edge2d<1>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_edge2d<0>, grid, dim3(256), 0, s, a);
+    if (a.rad == 1 && a.steps == 2) hipLaunchKernelGGL((k_edge2d<1, 2>), grid, dim3(256), 0, s, a);
+    else if (a.rad == 1) hipLaunchKernelGGL((k_edge2d<1, 3>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_edge2d<0, 2>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -46,8 +46,8 @@ struct DirectJob {
     int block0;
 };
 
-// Edge correction of a two-sweep fused launch on a 2-D zero-halo grid: the
-// points within r of an edge get the exact two-sweep value.
+// Edge correction of a fused launch of S sweeps on a 2-D zero-halo grid:
+// the points within r(S-1) of an edge get the exact S-sweep value.
 struct EdgeJob {
     const float *in;   // state the fused launch read
     float *out;        // the fused launch's output (band points overwritten)
@@ -59,6 +59,7 @@ struct EdgeArgs {
     int total;
     EdgeJob job[kMaxJobs];
     int rad;
+    int steps;         // S: 2, or 3 for radius 1
     const double *w;   // the unfused (2r+1)^2 coefficients
 };
 hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s);

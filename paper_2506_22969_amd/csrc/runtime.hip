@@ -526,10 +526,12 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     if (o.fuse_steps < 1 || o.fuse_steps > 8) return SS_E_INVALID;
     if (o.engine < SS_ENGINE_AUTO || o.engine > SS_ENGINE_DIRECT) return SS_E_INVALID;
     if ((o.r1 == 0) != (o.r2 == 0) || o.r1 < 0 || o.r2 < 0) return SS_E_INVALID;
-    // a zero halo fuses two 2-D sweeps of an FP32 state, with the edge band
-    // recomputed (the composed stencil is exact only away from the edges)
+    // a zero halo fuses 2-D sweeps of an FP32 state (two of any radius, or
+    // three of radius 1), with the band along the edges recomputed (the
+    // composed stencil is exact only farther than r(S-1) from the edges)
     const bool edge_fused = o.fuse_steps > 1 && o.boundary == SS_BC_ZERO;
-    if (edge_fused && (o.fuse_steps != 2 || ndim != 2 || (dtype != SS_F32_SPLIT_F16 && dtype != SS_F32_SPLIT_BF16)))
+    if (edge_fused && (o.fuse_steps > 3 || (o.fuse_steps == 3 && radius != 1) || ndim != 2 ||
+                       (dtype != SS_F32_SPLIT_F16 && dtype != SS_F32_SPLIT_BF16)))
         return SS_E_UNSUPPORTED;
     if (o.fuse_steps > 1 && !allow_fuse) return SS_E_INVALID;
     if (o.flags & ~SS_FLAG_HOST_ONLY) return SS_E_INVALID;
@@ -695,6 +697,7 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
     EdgeArgs ea{};
     ea.njobs = n;
     ea.rad = p->edge_rad;
+    ea.steps = p->fuse;
     ea.w = p->edge_w;
     for (int j = 0; j < n; ++j)
         ea.job[j] = EdgeJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],

@@ -223,28 +223,28 @@ FUSED_ZERO = [("box", (64, 64)), ("star", (300, 264)), ("box", (37, 41)), ("box"
 
 @pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
 @pytest.mark.parametrize("shape,dims", FUSED_ZERO)
-@pytest.mark.parametrize("steps", [6, 7])
-def test_two_step_fusion_with_zero_halo(engine, shape, dims, steps):
-    """Two fused sweeps on a zero-halo grid (the composed stencil everywhere,
-    then the band within r of an edge recomputed exactly) against the
-    unfused oracle; an odd step count ends with one unfused sweep."""
+@pytest.mark.parametrize("fuse,steps", [(2, 6), (2, 7), (3, 6), (3, 7)])
+def test_fusion_with_zero_halo(engine, shape, dims, fuse, steps):
+    """Fused sweeps on a zero-halo grid (the composed stencil everywhere,
+    then the band within r(S-1) of an edge recomputed exactly) against the
+    unfused oracle; leftover steps run unfused."""
     from oracle import tables as T
     w, _ = synthetic.random_coeffs(shape, 1, 2, seed=1, grid_shape=dims)
     x0 = synthetic.grid_f32(dims, seed=5)
-    with native.Plan(shape, 1, w, dims, "f32_split_f16", boundary="zero", fuse_steps=2, engine=engine) as p:
+    with native.Plan(shape, 1, w, dims, "f32_split_f16", boundary="zero", fuse_steps=fuse, engine=engine) as p:
         info = p.info
-        assert info["engine_name"] == engine and info["fuse_steps"] == 2 and info["k"] == 5
+        assert info["engine_name"] == engine and info["fuse_steps"] == fuse and info["k"] == 2 * fuse + 1
         assert info["launches_per_sweep"] == 2
         got = run_plan(p, x0, steps)
     ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=False)
     err = normwise_err(got, ref)
-    w2 = T.compose(np.asarray(w, dtype=np.float64), 2)
-    s1, s2 = float(np.abs(w).sum()), float(np.abs(w2).sum())
-    fused, rest = steps // 2, steps % 2
+    ws = T.compose(np.asarray(w, dtype=np.float64), fuse)
+    s1, ss = float(np.abs(w).sum()), float(np.abs(ws).sum())
+    fused, rest = steps // fuse, steps % fuse
     if engine == "direct":
-        tol = 2 * 2.0 ** -24 * (fused * (np.count_nonzero(w2) + 1) * s2 + rest * (np.count_nonzero(w) + 1) * s1)
+        tol = 2 * 2.0 ** -24 * (fused * (np.count_nonzero(ws) + 1) * ss + rest * (np.count_nonzero(w) + 1) * s1)
     else:
         b = split_step_bound("f16", n_mma_of(info))
-        tol = fused * b * s2 + rest * b * s1
-    print(f"engine={engine} {shape} dims={dims} steps={steps} err={err:.3e} tol={tol:.3e}")
+        tol = fused * b * ss + rest * b * s1
+    print(f"engine={engine} {shape} dims={dims} S={fuse} steps={steps} err={err:.3e} tol={tol:.3e}")
     assert err <= tol

@@ -185,16 +185,19 @@ def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
 
 
 def test_zero_halo_fusion_scope():
-    """Two fused sweeps with a zero halo: 2-D FP32-state plans only (the band
-    along the edges is a second launch); planes, 3-D and S = 3 stay
-    unsupported."""
+    """Fused sweeps with a zero halo: 2-D FP32-state plans only, S = 2 (any
+    radius) or S = 3 (radius 1), the band along the edges being a second
+    launch; planes, 3-D, S = 4 and S = 3 beyond radius 1 stay unsupported."""
     w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
     with native.Plan("box", 1, w, (64, 64), "f32_split_bf16", fuse_steps=2, host_only=True) as p:
         info = p.info
         assert info["fuse_steps"] == 2 and info["k"] == 5 and info["launches_per_sweep"] == 2
-    for dims, dtype, fuse in [((64, 64), "split_bf16", 2), ((64, 64), "f32_split_f16", 3)]:
+    with native.Plan("box", 1, w, (64, 64), "f32_split_f16", fuse_steps=3, host_only=True) as p:
+        assert p.info["k"] == 7 and p.info["launches_per_sweep"] == 2
+    w3r, _ = synthetic.random_coeffs("box", 3, 2, seed=1, grid_shape=(64, 64))
+    for rad, wr, dtype, fuse in [(1, w, "split_bf16", 2), (1, w, "f32_split_f16", 4), (3, w3r, "f32_split_f16", 3)]:
         with pytest.raises(native.SparStencilError):
-            native.Plan("box", 1, w, dims, dtype, fuse_steps=fuse, host_only=True)
+            native.Plan("box", rad, wr, (64, 64), dtype, fuse_steps=fuse, host_only=True)
     w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
     with pytest.raises(native.SparStencilError):
         native.Plan("box", 1, w3, (8, 8, 8), "f32_split_f16", fuse_steps=2, host_only=True)
