@@ -195,26 +195,29 @@ def test_box9_full_size_sampled():
     assert err <= tol
 
 
-def test_box9_full_size_fused_sampled():
-    # The benchmark's launch configuration: the same workload as two fused
-    # sweeps per launch plus the edge-band launch; sampled points include the
+@pytest.mark.parametrize("fuse", [2, 3])
+def test_box9_full_size_fused_sampled(fuse):
+    # The benchmark's launch configuration: the same workload with S sweeps
+    # fused per launch plus the edge-band launch; sampled points include the
     # corners and edges, whose values come from the edge-band launch.
     from oracle import tables as T
     dims = (10240, 10240)
     steps = 100
     w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
     x0 = synthetic.grid_f32(dims, seed=0)
-    with native.Plan("box", 1, w, dims, "f32_split_f16", fuse_steps=2) as p:
+    with native.Plan("box", 1, w, dims, "f32_split_f16", fuse_steps=fuse) as p:
         info = p.info
-        assert info["engine_name"] == "smfmac" and info["fuse_steps"] == 2
+        assert info["engine_name"] == "smfmac" and info["fuse_steps"] == fuse
         got = run_plan(p, x0, steps)
-    pts = sample_points(*dims, 16, seed=2) + [(0, 0), (0, 4321), (10239, 10239), (777, 0), (10239, 5), (3, 10238)]
+    pts = sample_points(*dims, 16, seed=2) + [(0, 4321), (777, 0), (10239, 5), (3, 10238), (1, 1), (10238, 10237)]
     ref = cone_sample(x0, w, steps, pts)
     vals = np.array([got[y, x] for (y, x) in pts], dtype=np.float64)
     err = float(np.abs(vals - ref).max() / np.abs(ref).max())
-    s2 = float(np.abs(T.compose(np.asarray(w, dtype=np.float64), 2)).sum())
-    tol = (steps // 2) * split_step_bound("f16", n_mma_of(info)) * s2
-    print(f"full-size fused sampled err={err:.3e} tol={tol:.3e}")
+    s1 = float(np.abs(w).sum())
+    ss = float(np.abs(T.compose(np.asarray(w, dtype=np.float64), fuse)).sum())
+    b = split_step_bound("f16", n_mma_of(info))
+    tol = (steps // fuse) * b * ss + (steps % fuse) * b * s1
+    print(f"full-size fused S={fuse} sampled err={err:.3e} tol={tol:.3e}")
     assert err <= tol
 
 
