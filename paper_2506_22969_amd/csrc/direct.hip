@@ -179,12 +179,16 @@ __global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
         constexpr int H = R * S;            // half width of the input square
         constexpr int E = 2 * H + 1;
         double cur[E][E];
+        // branch-free: every load is issued (at a clamped address) and
+        // out-of-grid values are selected away, so the loads overlap
 #pragma unroll
         for (int i = 0; i < E; ++i)
 #pragma unroll
             for (int c = 0; c < E; ++c) {
                 const int sy = y - H + i, sx = x - H + c;
-                cur[i][c] = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? (double)g.in[(size_t)sy * g.nx + sx] : 0.0;
+                const int cy = min(max(sy, 0), g.ny - 1), cx = min(max(sx, 0), g.nx - 1);
+                const float v = g.in[(size_t)cy * g.nx + cx];
+                cur[i][c] = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? (double)v : 0.0;
             }
         double w[K][K];
 #pragma unroll
@@ -202,12 +206,11 @@ __global__ __launch_bounds__(256) void k_edge2d(EdgeArgs a) {
                     if (i < H - h || i > H + h || c < H - h || c > H + h) continue;
                     const int sy = y - H + i, sx = x - H + c;
                     double v = 0.0;
-                    if (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) {
 #pragma unroll
-                        for (int dy = 0; dy < K; ++dy)
+                    for (int dy = 0; dy < K; ++dy)
 #pragma unroll
-                            for (int dx = 0; dx < K; ++dx) v += w[dy][dx] * cur[i - R + dy][c - R + dx];
-                    }
+                        for (int dx = 0; dx < K; ++dx) v += w[dy][dx] * cur[i - R + dy][c - R + dx];
+                    v = (sy >= 0 && sy < g.ny && sx >= 0 && sx < g.nx) ? v : 0.0;
                     // written in place from the outside in is unsafe, so
                     // results of this sweep go to the corner block first
                     cur[i - (H - h)][c - (H - h)] = v;
