@@ -47,8 +47,11 @@ def test_server_mix_matches_run_alone():
     dev = "cuda:0"
     w9, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(512, 512))
     w9b, _ = synthetic.random_coeffs("box", 1, 2, seed=5, grid_shape=(512, 512))
-    specs = [  # (coeffs, dims, dtype, engine, boundary, steps)
+    specs = [  # (coeffs, dims, dtype, engine, boundary, steps[, fused sweeps per launch])
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 7),
+        (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 11, 3),
+        (w9b, (300, 520), "f32_split_f16", "smfmac", "zero", 8, 3),
+        (w9, (130, 264), "f32_split_bf16", "mfma", "zero", 5, 2),
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 3),
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 12),
         (w9b, (300, 520), "f32_split_f16", "smfmac", "zero", 5),
@@ -63,10 +66,10 @@ def test_server_mix_matches_run_alone():
     ]
     plans, jobs = [], []
     w3 = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
-    for i, (w, dims, dtype, engine, bc, steps) in enumerate(specs):
+    for i, (w, dims, dtype, engine, bc, steps, *fuse) in enumerate(specs):
         if len(dims) == 3:  # 3-D box of radius 1
             w = w3
-        plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine)
+        plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine, fuse_steps=fuse[0] if fuse else 1)
         plans.append(plan)
         if dtype == "split_bf16":
             x0 = torch.from_numpy(synthetic.grid_bf16_planes(dims, seed=10 + i).view(np.int16)).to(dev)
