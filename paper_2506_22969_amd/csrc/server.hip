@@ -240,7 +240,9 @@ bool ss_server_::step() {
                 continue;
             }
             j->phase = kSweep;
-            j->advance = grp.first == j->plan ? j->plan->fuse : 1;
+            // the launched plan sets the sweeps (a job's own fused plan, or
+            // an equal-class plan of another job, or a leftover single sweep)
+            j->advance = grp.first->fuse;
             j->busy = true;
         }
         progress = true;

@@ -46,11 +46,15 @@ def test_server_mix_matches_run_alone():
     torch = pytest.importorskip("torch")
     dev = "cuda:0"
     w9, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(512, 512))
-    w9b, _ = synthetic.random_coeffs("box", 1, 2, seed=5, grid_shape=(512, 512))
+    w9b, _ = synthetic.random_coeffs("box", 1, 2, seed=20, grid_shape=(512, 512))
+    assert not np.array_equal(w9, w9b)
+    # jobs 1 and 2 are planned apart with equal coefficients: their fused
+    # launches batch together, each must still be credited three sweeps
     specs = [  # (coeffs, dims, dtype, engine, boundary, steps[, fused sweeps per launch])
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 7),
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 11, 3),
-        (w9b, (300, 520), "f32_split_f16", "smfmac", "zero", 8, 3),
+        (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 8, 3),
+        (w9b, (300, 520), "f32_split_f16", "smfmac", "zero", 10, 3),
         (w9, (130, 264), "f32_split_bf16", "mfma", "zero", 5, 2),
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 3),
         (w9, (300, 520), "f32_split_f16", "smfmac", "zero", 12),
