@@ -172,8 +172,10 @@ def timed_run(torch, plan, x_dev, steps, stream, reps=1):
 def workloads_leg(native, torch, stream):
     """The other workloads of the study on every engine that runs them:
     Heat-2D 256^2 FP64 (10 sweeps, zero halo), Star-2D13P / Box-2D49P on
-    8192^2 bfloat16 hi+lo planes (50 sweeps, 2-step fusion, periodic) and
-    Heat-3D / Box-3D27P on 512^3 FP32 (20 sweeps, zero halo).  Returns the
+    8192^2 bfloat16 hi+lo planes (50 sweeps, 2-step fusion, periodic),
+    Heat-3D / Box-3D27P on 512^3 FP32 (20 sweeps, zero halo) and 3- and
+    5-point 1-D stencils on 10,240,000 points (100 sweeps, zero halo, one or
+    three sweeps per launch).  Returns the
     timings and, per result, the inputs and GPU values at sampled points for
     the oracle check."""
     import synthetic
@@ -223,6 +225,19 @@ def workloads_leg(native, torch, stream):
         pts = [(0, 0, 0), (255, 100, 511), (511, 511, 3), (17, 300, 200)]
         record(name, shape, 1, w, (512, 512, 512), "f32_split_f16", 20, ["smfmac", "mfma", "direct"], x3,
                lambda h: torch.from_numpy(h).to("cuda:0"), False, pts=pts,
+               pick=lambda y, pt: float(y[pt].item()))
+    del x3
+    # 1-D on the paper's 10,240,000-point grids: a 3-point (Heat-1D shape)
+    # and a 5-point stencil, 100 sweeps with a zero halo, one sweep per
+    # launch and three fused sweeps per launch (plus the end-band launch)
+    n1 = 10_240_000
+    x1 = synthetic.grid_f32((n1,), seed=0)
+    for name, radius, fuse in [("heat1d3p_10240000_T100", 1, 1), ("heat1d3p_10240000_S3_T100", 1, 3),
+                               ("1d5p_10240000_T100", 2, 1), ("1d5p_10240000_S3_T100", 2, 3)]:
+        w = synthetic.random_coeffs("box", radius, 1, seed=3, grid_shape=(4096,))[0]
+        pts = [(0,), (4096,), (5_000_000,), (n1 - 1,)]
+        record(name, "box", radius, w, (n1,), "f32_split_f16", 100, ["smfmac", "mfma", "direct"], x1,
+               lambda h: torch.from_numpy(h).to("cuda:0"), False, fuse=fuse, reps=5, pts=pts,
                pick=lambda y, pt: float(y[pt].item()))
     return out, checks
 

@@ -66,10 +66,12 @@ typedef enum {
 typedef struct {
     uint32_t struct_size;  /* sizeof(ss_plan_opts)                               */
     int32_t boundary;      /* ss_boundary                                        */
-    int32_t fuse_steps;    /* S >= 1 sweeps composed into one: periodic grids,
-                              or S = 2 on a 2-D FP32-state (split) grid with a
-                              zero halo, where a second launch recomputes the
-                              points within r of an edge exactly              */
+    int32_t fuse_steps;    /* S >= 1 sweeps composed into one (at most 8):
+                              periodic grids; with a zero halo, FP32-state
+                              (split) grids only: 2-D with S = 2, or S = 3 at
+                              radius 1; 1-D with r*S <= 8.  A second launch
+                              then recomputes the points within r(S-1) of an
+                              edge exactly                                    */
     int32_t r1, r2;        /* tile width (x) and height (y); 0,0 = explore       */
     int32_t engine;        /* ss_engine                                          */
     uint32_t flags;        /* SS_FLAG_* bits, 0 by default                       */
@@ -97,9 +99,13 @@ typedef struct ss_plan_ *ss_plan_t;
  *
  * On success *out owns host and device tables until sparstencil_plan_destroy.
  * A plan is immutable and may be shared by threads.  Errors: SS_E_INVALID,
- * SS_E_UNSUPPORTED (e.g. no engine for the dtype/engine pair, S > 1 with a
- * zero halo other than S = 2 on a 2-D FP32-state grid, |coefficient| beyond
- * the binary16 range), SS_E_NOMEM, SS_E_DEVICE.
+ * SS_E_UNSUPPORTED (e.g. no engine for the dtype/engine pair, a zero-halo
+ * fusion outside the cases under fuse_steps, |coefficient| beyond the
+ * binary16 range), SS_E_NOMEM, SS_E_DEVICE.  The matrix-core engines take
+ * 2-D grids (FP32 split state or bfloat16 planes), 3-D grids (FP32 split
+ * state) and 1-D grids (FP32 split state, tiles of 16 outputs, composed
+ * radius up to 8); FP64 runs on MFMA for 2-D; the direct engine takes the
+ * rest.
  */
 ss_status sparstencil_plan(ss_plan_t *out, int32_t shape, int32_t radius, const double *coeffs,
                            int32_t ndim, const int64_t *grid_dims, int32_t dtype,

@@ -124,6 +124,7 @@ static hipError_t launch_r(DirectArgs &a, hipStream_t s) {
     if (r <= 1) return launch_t<KIND, 1>(a, s);
     if (r <= 2) return launch_t<KIND, 2>(a, s);
     if (r <= 3) return launch_t<KIND, 3>(a, s);
+    static_assert(kDirectMaxRad == 6, "widest instantiated radius");
     if (r <= 6) return launch_t<KIND, 6>(a, s);
     return hipErrorInvalidValue;
 }

@@ -1,0 +1,252 @@
+// 1-D stencil sweep as a structured-sparse (or dense) matrix product on
+// gfx950 matrix cores, FP32 state split into binary16 or bfloat16 hi + lo
+// parts as it is gathered (paper Sections 3.1-3.3 with one tile row).
+//
+// A tile is 16 consecutive outputs (r1 = 16, r2 = 1): A' is the 16 x (15+k)
+// band of the coefficients, and sixteen tiles (256 consecutive outputs) form
+// the N dimension of one MMA.  The work is a stream: every workgroup stages
+// 4096 outputs' inputs (plus 8 on each side) into LDS with 16-byte loads,
+// multiplies them out and writes the outputs back 16 bytes per lane, so the
+// sweep is bound by HBM like any 1-D stencil.
+//
+// LDS keeps one padding word after every 16 values: tile n of an MMA starts
+// 17n words after tile 0, so the sixteen B columns of a gather fall into
+// different banks.  The gather offset of patch column p is then
+// p + ((c0 + p) >> 4) for every tile, with c0 = 8 - radius.
+#include "mma2d_impl.hpp"
+
+namespace ss {
+namespace {
+
+constexpr int k1Threads = 256;
+constexpr int k1Block = 4096;                   // outputs per workgroup
+constexpr int k1Halo = 8;                       // staged inputs on each side
+constexpr int k1Span = k1Block + 2 * k1Halo;    // staged inputs
+constexpr int k1Words = k1Span + k1Span / 16 + 1;
+constexpr int k1PerWave = k1Block / (k1Threads / 64);   // outputs per wave
+static_assert(k1PerWave % 256 == 0, "a wave owns whole MMAs");
+
+__device__ inline int skewed(int i) { return i + (i >> 4); }
+
+template <int KC, int RAD, int MODE, int PART, int BC, bool VEC>
+__global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
+    static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
+    constexpr int VPK = (MODE == kSparse) ? 8 : 4;
+    __shared__ float lds[k1Words];
+
+    // the job of this workgroup (jobs' first blocks ascend)
+    int j = 0;
+    for (int t = 1; t < p.njobs; ++t) j = (int)blockIdx.x >= p.job[t].item0 ? t : j;
+    const MmaJob g = p.job[j];
+    const int n = g.nx;
+    const int base = ((int)blockIdx.x - g.item0) * k1Block;
+    // the grid is global memory: say so, so that the loads are global ones
+    const __attribute__((address_space(1))) float *x =
+        (const __attribute__((address_space(1))) float *)static_cast<const float *>(g.in);
+    const int tid = threadIdx.x;
+
+    // stage x[base - 8, base + 4104): 16-byte loads away from the ends,
+    // element by element (zero or wrapped) near them
+    const int first = base - k1Halo;
+    if (VEC && first >= 0 && first + k1Span <= n) {
+        constexpr int NV = k1Span / 4;
+        constexpr int PER = (NV + k1Threads - 1) / k1Threads;
+        f4 v[PER];
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = tid + r * k1Threads;
+            if (i < NV) v[r] = *(const __attribute__((address_space(1))) f4 *)(x + first + 4 * i);
+        }
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int i = tid + r * k1Threads;
+            if (i < NV) {
+                // four values of one 16-value run: consecutive words
+                float *d = lds + skewed(4 * i);
+                d[0] = v[r].x;
+                d[1] = v[r].y;
+                d[2] = v[r].z;
+                d[3] = v[r].w;
+            }
+        }
+    } else {
+        for (int i = tid; i < k1Span; i += k1Threads) {
+            const int gi = first + i;
+            float v = 0.0f;
+            if (gi >= 0 && gi < n) v = x[gi];
+            else if constexpr (BC != kBcZero) v = x[wrap<kBcWrapN>(gi, n)];
+            lds[skewed(i)] = v;
+        }
+    }
+
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int q = lane >> 4;
+    const int tile = lane & 15;
+    // A fragments and per-lane gather offsets (words from the tile's first
+    // patch word; each B register reads two patch columns p, p + 1)
+    uint4 ahi[KC], alo[KC];
+    unsigned aidx[KC];
+    int off[KC][VPK][2];
+    constexpr int c0 = k1Halo - RAD;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+        ahi[kc] = p.a_hi[kc * 64 + lane];
+        alo[kc] = p.a_lo[kc * 64 + lane];
+        aidx[kc] = MODE == kSparse ? p.a_idx[kc * 64 + lane] : 0u;
+#pragma unroll
+        for (int v = 0; v < VPK; ++v) {
+            const int pc = p.boff[(kc * 4 + q) * VPK + v] >> 2;
+            off[kc][v][0] = pc + ((c0 + pc) >> 4);
+            off[kc][v][1] = pc + 1 + ((c0 + pc + 1) >> 4);
+        }
+    }
+    const float sigma = 1.0f / p.inv_sigma;
+    const float inv_sigma = p.inv_sigma;
+    __syncthreads();
+
+    // outputs of this block that exist, and a store descriptor over them
+    const int valid = min(k1Block, n - base);
+    float *out = static_cast<float *>(g.out) + base;
+    const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, valid * 4);
+#pragma unroll 1
+    for (int u = 0; u < k1PerWave / 256; ++u) {
+        const int o0 = wave * k1PerWave + u * 256;     // first output of the MMA
+        // first patch word of this lane's tile: staged index c0 + o0 + 16 tile
+        const float *tb = lds + (c0 + 17 * ((o0 >> 4) + tile));
+        f4 accm = {0.f, 0.f, 0.f, 0.f}, acc1 = accm, acc2 = accm;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+            unsigned bh[VPK], bl[VPK];
+#pragma unroll
+            for (int v = 0; v < VPK; ++v) split2<PART>(tb[off[kc][v][0]], tb[off[kc][v][1]], sigma, &bh[v], &bl[v]);
+            accm = mma<MODE, PART>(ahi[kc], bh, accm, aidx[kc]);
+            acc1 = mma<MODE, PART>(ahi[kc], bl, acc1, aidx[kc]);
+            acc2 = mma<MODE, PART>(alo[kc], bh, acc2, aidx[kc]);
+        }
+        // accumulator rows 4q..4q+3 are outputs o0 + 16 tile + 4q + i
+        const int o = o0 + 16 * tile + 4 * q;
+        float ys[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ys[i] = accm[i] + (acc1[i] + acc2[i]) * inv_sigma;
+        if constexpr (VEC) {
+            const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
+                            __float_as_uint(ys[3])};
+            __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o < valid ? (unsigned)o * 4u : kOob, 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc,
+                                                      o + i < valid ? (unsigned)(o + i) * 4u : kOob, 0, 0);
+        }
+    }
+}
+
+template <int KC, int RAD, int MODE, int PART>
+hipError_t launch_mma1d(MmaArgs &a, hipStream_t s) {
+    if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
+    int blocks = 0;
+    bool vec = true;
+    for (int j = 0; j < a.njobs; ++j) {
+        MmaJob &g = a.job[j];
+        if (g.nx < 1) return hipErrorInvalidValue;
+        g.item0 = blocks;
+        blocks += (g.nx + k1Block - 1) / k1Block;
+        // 16-byte loads and stores need 16-byte aligned grids of whole float4s
+        vec = vec && g.nx % 4 == 0 && ((uintptr_t)g.in % 16) == 0 && ((uintptr_t)g.out % 16) == 0;
+    }
+    a.total_items = blocks;
+    const dim3 grid(blocks), block(k1Threads);
+    if (a.periodic) {
+        if (vec) hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcWrapN, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcWrapN, false>), grid, block, 0, s, a);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcZero, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcZero, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <int RAD>
+MmaLaunch pick1d(int mode, int part) {
+    if (mode == kSparse) return part == kPartF16 ? &launch_mma1d<1, RAD, kSparse, kPartF16>
+                                                 : &launch_mma1d<1, RAD, kSparse, kPartBF16>;
+    return part == kPartF16 ? &launch_mma1d<1, RAD, kDense, kPartF16> : &launch_mma1d<1, RAD, kDense, kPartBF16>;
+}
+
+// Exact values of the points within r(S-1) of either end after S zero-halo
+// sweeps, one thread per point: the window of inputs the point depends on
+// is swept S times in FP64 in LDS, shrinking by r on each side per sweep,
+// with the points outside the grid held at zero.
+constexpr int kEdge1Threads = 64;
+constexpr int kEdge1Win = 2 * k1Halo + 1;
+
+__global__ __launch_bounds__(kEdge1Threads) void k_edge1d(EdgeArgs a) {
+    __shared__ double buf[2][kEdge1Win][kEdge1Threads];
+    const int t = blockIdx.x * kEdge1Threads + threadIdx.x;
+    if (t >= a.total) return;
+    int j = 0;
+    for (int i = 1; i < a.njobs; ++i) j = t >= a.job[i].point0 ? i : j;
+    const EdgeJob g = a.job[j];
+    const int n = g.nx;
+    const int R = a.rad * a.steps;            // composed radius
+    const int b = a.rad * (a.steps - 1);      // band width
+    const int lo_count = min(b, n);
+    const int i = t - g.point0;
+    const int pt = i < lo_count ? i : n - (i - lo_count) - 1;
+    const int L = 2 * R + 1;
+    const int k = 2 * a.rad + 1;
+    double(*cur)[kEdge1Threads] = buf[0];
+    double(*nxt)[kEdge1Threads] = buf[1];
+    for (int w = 0; w < L; ++w) {
+        const int gi = pt - R + w;
+        cur[w][threadIdx.x] = (gi >= 0 && gi < n) ? (double)g.in[gi] : 0.0;
+    }
+    for (int s = 1; s <= a.steps; ++s) {
+        for (int w = s * a.rad; w < L - s * a.rad; ++w) {
+            const int gi = pt - R + w;
+            double acc = 0.0;
+            for (int o = 0; o < k; ++o) acc += a.w[o] * cur[w + o - a.rad][threadIdx.x];
+            nxt[w][threadIdx.x] = (gi >= 0 && gi < n) ? acc : 0.0;
+        }
+        double(*tmp)[kEdge1Threads] = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    g.out[pt] = (float)cur[R][threadIdx.x];
+}
+
+}  // namespace
+
+MmaLaunch find_mma1d(int rad, int mode, int part) {
+    switch (rad) {
+        case 1: return pick1d<1>(mode, part);
+        case 2: return pick1d<2>(mode, part);
+        case 3: return pick1d<3>(mode, part);
+        case 4: return pick1d<4>(mode, part);
+        case 5: return pick1d<5>(mode, part);
+        case 6: return pick1d<6>(mode, part);
+        case 7: return pick1d<7>(mode, part);
+        case 8: return pick1d<8>(mode, part);
+        default: return nullptr;
+    }
+}
+
+hipError_t launch_edge1d(EdgeArgs &a, hipStream_t s) {
+    if (a.njobs < 1 || a.njobs > kMaxJobs || a.steps < 2 || a.rad < 1 || a.rad * a.steps > k1Halo)
+        return hipErrorInvalidValue;
+    const int b = a.rad * (a.steps - 1);
+    int total = 0;
+    for (int j = 0; j < a.njobs; ++j) {
+        EdgeJob &g = a.job[j];
+        if (g.nx < 1 || g.ny != 1) return hipErrorInvalidValue;
+        g.point0 = total;
+        total += min(2 * b, g.nx);
+    }
+    a.total = total;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge1d, dim3((total + kEdge1Threads - 1) / kEdge1Threads), dim3(kEdge1Threads), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ss

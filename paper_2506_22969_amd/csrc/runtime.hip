@@ -463,6 +463,93 @@ ss_status plan_mma2d_f64(ss_plan_ *p) {
     return SS_OK;
 }
 
+// K order of the 1-D kernels (tile of 16 outputs, g = 15 + k patch
+// columns, g even).  Sparse: adjacent column pairs (2j, 2j+1), so that one
+// B register holds two neighbouring inputs, each 4-group two such pairs at
+// least k + 1 columns apart (then no row of the band has more than the two
+// values of one pair in a group), unmatched pairs beside zero columns.
+// Dense: natural order.  Both padded with zero columns to one K chunk.
+std::vector<int> order_1d(const Geometry &gm, int k, int mode) {
+    std::vector<int> order;
+    if (mode == kDense) {
+        for (int c = 0; c < gm.g; ++c) order.push_back(c);
+        order.resize(32, kZeta);
+        return order;
+    }
+    const int npairs = gm.g / 2, gap = (k + 2) / 2;   // 2 * gap >= k + 1
+    std::vector<char> used(npairs, 0);
+    for (int a = 0; a < npairs; ++a) {
+        if (used[a]) continue;
+        used[a] = 1;
+        int b = -1;
+        for (int t = a + gap; t < npairs && b < 0; ++t)
+            if (!used[t]) b = t;
+        if (b >= 0) used[b] = 1;
+        order.push_back(2 * a);
+        order.push_back(2 * a + 1);
+        order.push_back(b >= 0 ? 2 * b : kZeta);
+        order.push_back(b >= 0 ? 2 * b + 1 : kZeta);
+    }
+    order.resize(64, kZeta);
+    return order;
+}
+
+// 1-D MMA engines (FP32 state, binary16 or bfloat16 split): tile (16, 1),
+// one K chunk, composed radius up to 8.
+ss_status plan_mma1d(ss_plan_ *p, int engine) {
+    if (p->ndim != 1 || p->rad > 8) return SS_E_UNSUPPORTED;
+    if (p->info.r1 && (p->info.r1 != 16 || p->info.r2 != 1)) return SS_E_UNSUPPORTED;
+    const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
+    const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    const Geometry gm = make_geometry(1, p->k, 16, 1);
+    ModelParams mp{};
+    mp.ndim = 1;
+    mp.k = p->k;
+    mp.dims[0] = p->dims[2];
+    mp.dims[1] = mp.dims[2] = 1;
+    mp.elem_bytes = 4;
+    mp.planes_state = 1;
+    mp.coef_bytes = 2;
+    mp.passes = 3;
+    mp.kfrag = 64;
+    const ModelRow r = model_time(mp, 16, 1);
+    const double row[7] = {(double)r.r1, (double)r.r2, r.t, r.t_compute, r.t_global, r.t_shared, (double)r.k_pad};
+    p->model.assign(row, row + 7);
+    ss_status st = build_canonical(p, gm, part, 64);
+    if (st != SS_OK) return st;
+    const std::vector<int> kperm = order_1d(gm, p->k, mode);
+    p->kperm.assign(kperm.begin(), kperm.end());
+    std::vector<uint8_t> blob;
+    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    st = build_mma_tables(p, gm, kperm, mode, part, 1, 0, false, &blob, &o_hi, &o_lo, &o_idx, &o_boff, &o_zero);
+    if (st != SS_OK) return st;
+    const MmaLaunch fn = find_mma1d(p->rad, mode, part);
+    if (!fn) return SS_E_UNSUPPORTED;
+    st = upload(p, blob);
+    if (st != SS_OK) return st;
+    char *d = static_cast<char *>(p->dev);
+    p->mma = fn;
+    p->margs.periodic = p->boundary == SS_BC_PERIODIC;
+    p->margs.inv_sigma = part == kPartF16 ? 1.0f / 2048.0f : 1.0f;
+    p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
+    p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
+    p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
+    p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
+    p->margs.zeros = d + o_zero;
+    p->engine = engine;
+    p->info.r1 = gm.r1;
+    p->info.r2 = gm.r2;
+    p->info.m_b = gm.m_b;
+    p->info.g = gm.g;
+    p->info.planes = gm.planes;
+    p->info.m_prime = gm.m_prime();
+    p->info.k_prime = gm.k_prime();
+    p->info.k_pad = (int)p->perm.size();
+    p->info.passes = 3;
+    p->info.sigma = part == kPartF16 ? 2048.0 : 1.0;
+    return SS_OK;
+}
+
 ss_status plan_direct(ss_plan_ *p) {
     const bool f64 = p->dtype == SS_F64;
     // 2-D FP32-state or plane grids and 3-D FP32-state grids run on the
@@ -473,6 +560,7 @@ ss_status plan_direct(ss_plan_ *p) {
     if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0) && slab_offsets_fit(p))
         lds = find_lds_direct2d(p->rad, state);
     if (!f64 && p->ndim == 3 && state == kStateF32 && slab_offsets_fit(p)) lds = find_lds_direct3d(p->rad);
+    if (!lds && p->rad > kDirectMaxRad) return SS_E_UNSUPPORTED;
     const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
     const size_t o_zero = (wbytes + 255) & ~(size_t)255;
     std::vector<uint8_t> blob(o_zero + 1024, 0);
@@ -530,8 +618,9 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     // three of radius 1), with the band along the edges recomputed (the
     // composed stencil is exact only farther than r(S-1) from the edges)
     const bool edge_fused = o.fuse_steps > 1 && o.boundary == SS_BC_ZERO;
-    if (edge_fused && (o.fuse_steps > 3 || (o.fuse_steps == 3 && radius != 1) || ndim != 2 ||
-                       (dtype != SS_F32_SPLIT_F16 && dtype != SS_F32_SPLIT_BF16)))
+    const bool f32_split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16;
+    if (edge_fused && !(f32_split && ((ndim == 2 && (o.fuse_steps == 2 || (o.fuse_steps == 3 && radius == 1))) ||
+                                      (ndim == 1 && radius * o.fuse_steps <= 8))))
         return SS_E_UNSUPPORTED;
     if (o.fuse_steps > 1 && !allow_fuse) return SS_E_INVALID;
     if (o.flags & ~SS_FLAG_HOST_ONLY) return SS_E_INVALID;
@@ -596,6 +685,11 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
         if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma3d(p, SS_ENGINE_MFMA);
     } else if (split3 && ndim == 3 && engine == SS_ENGINE_MFMA) {
         st = plan_mma3d(p, SS_ENGINE_MFMA);
+    } else if (split3 && ndim == 1 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
+        st = plan_mma1d(p, SS_ENGINE_SMFMAC);
+        if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma1d(p, SS_ENGINE_MFMA);
+    } else if (split3 && ndim == 1 && engine == SS_ENGINE_MFMA) {
+        st = plan_mma1d(p, SS_ENGINE_MFMA);
     } else if (dtype == SS_F64 && ndim == 2 && engine == SS_ENGINE_MFMA) {
         st = plan_mma2d_f64(p);
     }
@@ -702,7 +796,7 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
     for (int j = 0; j < n; ++j)
         ea.job[j] = EdgeJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],
                             (int)dims[j][2], 0};
-    return launch_edge2d(ea, s);
+    return p->ndim == 1 ? launch_edge1d(ea, s) : launch_edge2d(ea, s);
 }
 
 hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {

@@ -201,3 +201,60 @@ def test_zero_halo_fusion_scope():
     w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
     with pytest.raises(native.SparStencilError):
         native.Plan("box", 1, w3, (8, 8, 8), "f32_split_f16", fuse_steps=2, host_only=True)
+
+
+@pytest.mark.parametrize("radius,fuse", [(1, 1), (2, 1), (1, 3), (2, 3), (4, 2), (8, 1)])
+@pytest.mark.parametrize("engine", ["smfmac", "mfma"])
+def test_1d_kernel_order_is_a_valid_layout(radius, fuse, engine):
+    """The 1-D kernels' K order (one chunk) holds every column of the
+    oracle's A' (16 x (15 + k)) once, pairs horizontally adjacent columns in
+    each B register, and (sparse) leaves at most two nonzeros of any A' row
+    in every 4-group."""
+    from oracle import tables as T
+    n = 5000
+    w, _ = synthetic.random_coeffs("box", radius, 1, seed=3, grid_shape=(4096,))
+    kw = dict(boundary="periodic", fuse_steps=fuse) if fuse > 1 else {}
+    with native.Plan("box", radius, w, (n,), "f32_split_f16", engine=engine, host_only=True, **kw) as p:
+        info = p.info
+        order = p.table(native.Q_KERNEL_PERM)
+        wk = p.table(native.Q_COEFFS)
+    assert info["engine_name"] == engine and (info["r1"], info["r2"]) == (16, 1)
+    assert info["k"] == 2 * radius * fuse + 1
+    a, s, d = T.morph(wk.reshape(info["k"]), 16, 1)
+    assert a.shape == (16, 15 + info["k"])
+    assert len(order) == (64 if engine == "smfmac" else 32)
+    used = sorted(int(c) for c in order if c >= 0)
+    assert used == list(range(a.shape[1]))
+    for v in range(0, len(order), 2):
+        c0, c1 = int(order[v]), int(order[v + 1])
+        assert (c0 < 0 and c1 < 0) or (c0 >= 0 and c1 == c0 + 1)
+    if engine == "smfmac":
+        for gq in range(0, len(order), 4):
+            cols = [int(c) for c in order[gq:gq + 4] if c >= 0]
+            assert np.all(np.count_nonzero(a[:, cols], axis=1) <= 2)
+
+
+def test_1d_zero_halo_fusion_scope():
+    """1-D zero-halo fusion: any S with r*S <= 8 (the staged halo), the two
+    end bands recomputed by a second launch; beyond that it is rejected."""
+    w1, _ = synthetic.random_coeffs("box", 1, 1, seed=3, grid_shape=(4096,))
+    w3, _ = synthetic.random_coeffs("box", 3, 1, seed=3, grid_shape=(4096,))
+    with native.Plan("box", 1, w1, (1000,), "f32_split_f16", fuse_steps=8, host_only=True) as p:
+        assert p.info["launches_per_sweep"] == 2 and p.info["k"] == 17
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 3, w3, (1000,), "f32_split_f16", fuse_steps=3, host_only=True)
+    with native.Plan("box", 3, w3, (1000,), "f32_split_bf16", host_only=True) as p:
+        assert p.info["engine_name"] == "smfmac" and p.info["launches_per_sweep"] == 1
+
+
+def test_direct_engine_refuses_radii_beyond_its_kernels():
+    """The direct kernels go up to radius 6; a wider plan on that engine is
+    refused when it is made, not when it runs."""
+    w7 = np.zeros((15, 15))
+    w7[7, :] = 1.0 / 15
+    with pytest.raises(native.SparStencilError):
+        native.Plan("box", 7, w7, (100, 100), "f32", engine="direct", host_only=True)
+    w6 = np.zeros((13, 13))
+    w6[6, :] = 1.0 / 13
+    with native.Plan("box", 6, w6, (100, 100), "f32", engine="direct", host_only=True) as p:
+        assert p.info["engine_name"] == "direct"
