@@ -52,7 +52,7 @@ def parse():
                     help="Poisson arrival rate as a fraction of the measured batch capacity")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
-    ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p"],
+    ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p", "heat1d3p", "1d5p"],
                     help="only copy the grid once and run four sweeps of one workload on the sparse engine (for profilers)")
     return ap.parse_args()
 
@@ -398,6 +398,11 @@ def profile_only(name: str, fuse: int):
         x = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
         plan = native.Plan("box", 3, w, (8192, 8192), "split_bf16", boundary="periodic", fuse_steps=2,
                            engine="smfmac")
+    elif name in ("heat1d3p", "1d5p"):
+        radius = 1 if name == "heat1d3p" else 2
+        w = synthetic.random_coeffs("box", radius, 1, seed=3, grid_shape=(4096,))[0]
+        x = torch.from_numpy(synthetic.grid_f32((10_240_000,), seed=0)).to("cuda:0")
+        plan = native.Plan("box", radius, w, (10_240_000,), "f32_split_f16", engine="smfmac")
     else:
         w = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
         x = torch.from_numpy(synthetic.grid_f32((512, 512, 512), seed=0)).to("cuda:0")

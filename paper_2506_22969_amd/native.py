@@ -80,6 +80,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python paper_2506_22969_amd/build.py")
+        # torch ships its own HIP and HSA runtime libraries.  Loaded after
+        # this library, torch's HIP runtime binds to the HSA runtime this
+        # library already brought in and finds no GPU; loaded first, both
+        # work.  So torch, when installed, is loaded before this library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
         L.sparstencil_plan.restype = i32

@@ -67,12 +67,17 @@ def test_server_mix_matches_run_alone():
         ("3d", (24, 48, 264), "f32_split_f16", "smfmac", "zero", 4),
         (w9, (64, 264), "split_bf16", "smfmac", "periodic", 3),
         (w9, (96, 264), "split_bf16", "smfmac", "periodic", 6),
+        ("1d", (100003,), "f32_split_f16", "smfmac", "zero", 7, 3),
+        ("1d", (4096,), "f32_split_bf16", "mfma", "periodic", 5),
     ]
     plans, jobs = [], []
     w3 = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
+    w1 = synthetic.random_coeffs("box", 1, 1, seed=3, grid_shape=(4096,))[0]
     for i, (w, dims, dtype, engine, bc, steps, *fuse) in enumerate(specs):
         if len(dims) == 3:  # 3-D box of radius 1
             w = w3
+        elif len(dims) == 1:
+            w = w1
         plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine, fuse_steps=fuse[0] if fuse else 1)
         plans.append(plan)
         if dtype == "split_bf16":
