@@ -37,6 +37,11 @@ struct MmaArgs {
     const int32_t *boff;     // [KC][4][VPK] gather offsets in bytes
     const void *zeros;       // 1 KiB of zeros (loads outside a zero-halo grid)
     const float *w;          // (2r+1)^2 coefficients (direct LDS kernel only)
+    // 1-D fused zero-halo sweeps: the unfused coefficients (FP64), radius and
+    // S; the launch then also recomputes the r(S-1) points at either end
+    // (nullptr: no end band)
+    const double *edge_w;
+    int edge_rad, edge_steps;
 };
 
 struct DirectJob {

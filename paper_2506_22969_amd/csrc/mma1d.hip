@@ -28,11 +28,65 @@ static_assert(k1PerWave % 256 == 0, "a wave owns whole MMAs");
 
 __device__ inline int skewed(int i) { return i + (i >> 4); }
 
+// Exact values of the points within r(S-1) of either end of every grid after
+// S zero-halo sweeps, by threads 0..63 of one workgroup, one point at a time
+// per thread: the window of inputs the point depends on is swept S times in
+// FP64 (in LDS, shrinking by r on each side per sweep) with the points
+// outside the grid held at zero.
+constexpr int kEdgeWin = 2 * k1Halo + 1;
+constexpr int kEdgeLanes = 64;
+
+__device__ inline int band_width(const MmaArgs &p) { return p.edge_rad * (p.edge_steps - 1); }
+
+__device__ inline void end_bands(const MmaArgs &p, double (*buf)[kEdgeWin][kEdgeLanes]) {
+    const int lane = threadIdx.x;
+    if (lane >= kEdgeLanes) return;
+    const int b = band_width(p);
+    const int R = p.edge_rad * p.edge_steps;
+    const int L = 2 * R + 1, k = 2 * p.edge_rad + 1;
+    for (int j = 0; j < p.njobs; ++j) {
+        const MmaJob g = p.job[j];
+        const int n = g.nx;
+        const int lo_count = min(b, n);
+        const int count = min(2 * b, n);
+        const float *in = static_cast<const float *>(g.in);
+        float *out = static_cast<float *>(g.out);
+        for (int i = lane; i < count; i += kEdgeLanes) {
+            const int pt = i < lo_count ? i : n - (i - lo_count) - 1;
+            double(*cur)[kEdgeLanes] = buf[0];
+            double(*nxt)[kEdgeLanes] = buf[1];
+            for (int w = 0; w < L; ++w) {
+                const int gi = pt - R + w;
+                cur[w][lane] = (gi >= 0 && gi < n) ? (double)in[gi] : 0.0;
+            }
+            for (int s = 1; s <= p.edge_steps; ++s) {
+                for (int w = s * p.edge_rad; w < L - s * p.edge_rad; ++w) {
+                    const int gi = pt - R + w;
+                    double acc = 0.0;
+                    for (int o = 0; o < k; ++o) acc += p.edge_w[o] * cur[w + o - p.edge_rad][lane];
+                    nxt[w][lane] = (gi >= 0 && gi < n) ? acc : 0.0;
+                }
+                double(*tmp)[kEdgeLanes] = cur;
+                cur = nxt;
+                nxt = tmp;
+            }
+            out[pt] = (float)cur[R][lane];
+        }
+    }
+}
+
 template <int KC, int RAD, int MODE, int PART, int BC, bool VEC>
 __global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
     static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
-    __shared__ float lds[k1Words];
+    __shared__ __attribute__((aligned(16))) float lds[k1Words];
+    static_assert(sizeof(float) * k1Words >= sizeof(double) * 2 * kEdgeWin * kEdgeLanes, "end-band buffers fit");
+
+    // the workgroup after the last block recomputes the end bands
+    if (p.edge_w && (int)blockIdx.x == p.total_items) {
+        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
+        return;
+    }
 
     // the job of this workgroup (jobs' first blocks ascend)
     int j = 0;
@@ -105,10 +159,16 @@ __global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
     const float inv_sigma = p.inv_sigma;
     __syncthreads();
 
-    // outputs of this block that exist, and a store descriptor over them
+    // outputs of this block that exist, and a store descriptor over them;
+    // the end bands of a fused zero-halo launch are left to the last
+    // workgroup (outputs [0, lo_end) and [hi_start, n))
     const int valid = min(k1Block, n - base);
     float *out = static_cast<float *>(g.out) + base;
     const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, valid * 4);
+    const int bw = p.edge_w ? band_width(p) : 0;
+    const int lo_end = min(bw, n) - base;
+    const int hi_start = max(n - bw, min(bw, n)) - base;
+    const bool plain = lo_end <= 0 && hi_start >= valid;
 #pragma unroll 1
     for (int u = 0; u < k1PerWave / 256; ++u) {
         const int o0 = wave * k1PerWave + u * 256;     // first output of the MMA
@@ -129,15 +189,18 @@ __global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
         float ys[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ys[i] = accm[i] + (acc1[i] + acc2[i]) * inv_sigma;
-        if constexpr (VEC) {
+        if (VEC && plain) {
             const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
                             __float_as_uint(ys[3])};
             __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o < valid ? (unsigned)o * 4u : kOob, 0, 0);
         } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc,
-                                                      o + i < valid ? (unsigned)(o + i) * 4u : kOob, 0, 0);
+            for (int i = 0; i < 4; ++i) {
+                const int oi = o + i;
+                const bool keep = oi < valid && oi >= lo_end && oi < hi_start;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc, keep ? (unsigned)oi * 4u : kOob,
+                                                      0, 0);
+            }
         }
     }
 }
@@ -156,7 +219,10 @@ hipError_t launch_mma1d(MmaArgs &a, hipStream_t s) {
         vec = vec && g.nx % 4 == 0 && ((uintptr_t)g.in % 16) == 0 && ((uintptr_t)g.out % 16) == 0;
     }
     a.total_items = blocks;
-    const dim3 grid(blocks), block(k1Threads);
+    // fused zero-halo sweeps: one more workgroup for the end bands
+    if (a.edge_w && (a.edge_steps < 2 || a.edge_rad < 1 || a.edge_rad * a.edge_steps > k1Halo))
+        return hipErrorInvalidValue;
+    const dim3 grid(blocks + (a.edge_w ? 1 : 0)), block(k1Threads);
     if (a.periodic) {
         if (vec) hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcWrapN, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_mma1d<KC, RAD, MODE, PART, kBcWrapN, false>), grid, block, 0, s, a);

@@ -730,7 +730,7 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     inf.engine = p->engine;
     inf.dtype = dtype;
     inf.boundary = p->boundary;
-    inf.launches_per_sweep = p->edge_rad ? 2 : 1;
+    inf.launches_per_sweep = p->edge_rad && !(p->ndim == 1 && p->mma) ? 2 : 1;
     for (int d = 0; d < 3; ++d) inf.dims[d] = p->dims[d];
     // plans with the same class share device-table contents: their grids can
     // be swept by one launch
@@ -784,7 +784,14 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
         a.njobs = n;
         for (int j = 0; j < n; ++j)
             a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
+        // the 1-D matrix kernels recompute the end bands in the same launch
+        if (p->ndim == 1 && p->edge_w) {
+            a.edge_w = p->edge_w;
+            a.edge_rad = p->edge_rad;
+            a.edge_steps = p->fuse;
+        }
         e = p->mma(a, s);
+        if (p->ndim == 1) return e;
     }
     // zero-halo fused sweeps: exact values for the band along the edges
     if (e != hipSuccess || !p->edge_w) return e;

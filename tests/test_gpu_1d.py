@@ -130,7 +130,8 @@ def test_1d_fused(engine, radius, fuse, n, boundary):
                      engine=engine) as p:
         info = p.info
         assert info["fuse_steps"] == fuse and info["k"] == 2 * radius * fuse + 1
-        assert info["launches_per_sweep"] == (2 if boundary == "zero" else 1)
+        # the matrix kernels recompute the end bands in the sweep's own launch
+        assert info["launches_per_sweep"] == (2 if boundary == "zero" and engine == "direct" else 1)
         got = run_plan(p, x0, steps)
     ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=boundary == "periodic")
     err = normwise_err(got, ref)
