@@ -283,8 +283,8 @@ SERVE_DTYPES = {"f32": "f32_split_f16", "split_bf16": "f32_split_bf16"}
 
 def serving_leg(native, torch, n_jobs: int, load: float):
     """Serving mix: jobs of several stencils, sizes, step counts and dtypes
-    through one server (2-D radius-1 jobs with three sweeps fused per
-    launch).  Three passes over the same jobs: all submitted at
+    through one server (2-D radius-1 and 1-D jobs with three sweeps fused
+    per launch).  Three passes over the same jobs: all submitted at
     once (batch capacity), one job at a time through sparstencil_run, and
     Poisson arrivals at `load` x the batch capacity (latency percentiles from
     arrival to result)."""
@@ -304,9 +304,9 @@ def serving_leg(native, torch, n_jobs: int, load: float):
             if ck not in coeffs:
                 coeffs[ck] = synthetic.random_coeffs(j["shape"], j["radius"], j["ndim"], seed=j["coeff_seed"],
                                                      grid_shape=j["grid"])[0]
-            # 2-D radius-1 jobs fuse three sweeps per launch (zero halo, edge
-            # band recomputed), as the headline workload does
-            fuse = 3 if j["ndim"] == 2 and j["radius"] == 1 else 1
+            # 2-D radius-1 and 1-D jobs fuse three sweeps per launch (zero
+            # halo, edge band recomputed), as the headline workload does
+            fuse = 3 if (j["ndim"] == 2 and j["radius"] == 1) or (j["ndim"] == 1 and 3 * j["radius"] <= 8) else 1
             plans[key] = native.Plan(j["shape"], j["radius"], coeffs[ck], j["grid"], SERVE_DTYPES[j["dtype"]],
                                      fuse_steps=fuse)
         if j["grid"] not in inputs:
