@@ -71,9 +71,8 @@ typedef struct {
                               (split) grids only: 2-D with S = 2, or S = 3 at
                               radius 1; 1-D with r*S <= 8.  The points
                               within r(S-1) of an edge are then recomputed
-                              exactly: by a second launch, or on the 1-D
-                              matrix engines by one more workgroup of the
-                              sweep's launch                                  */
+                              exactly: by a second launch (2-D), or by one
+                              more workgroup of the sweep's launch (1-D)      */
     int32_t r1, r2;        /* tile width (x) and height (y); 0,0 = explore       */
     int32_t engine;        /* ss_engine                                          */
     uint32_t flags;        /* SS_FLAG_* bits, 0 by default                       */

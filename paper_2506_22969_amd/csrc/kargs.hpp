@@ -68,9 +68,6 @@ struct EdgeArgs {
     const double *w;   // the unfused (2r+1)^2 coefficients
 };
 hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s);
-// The same for a 1-D grid (ny = 1): the points within r(S-1) of either
-// end, for r*S up to 8.
-hipError_t launch_edge1d(EdgeArgs &a, hipStream_t s);
 
 // Direct sweep: one (2r+1)^3 box (r = 0 on missing axes), radius up to
 // kDirectMaxRad.
@@ -119,6 +116,9 @@ MmaLaunch find_lds_direct3d(int rad);
 // 1-D MMA sweep (FP32 state, tile of 16 outputs, one K chunk) for radius
 // 1..8; nullptr beyond.  The launch fills total_items and the jobs' item0.
 MmaLaunch find_mma1d(int rad, int mode, int part);
+// Direct 1-D sweep (FP32 state) from the same staging, radius 1..8,
+// coefficients in MmaArgs::w; nullptr beyond.
+MmaLaunch find_lds_direct1d(int rad);
 
 // Dense FP64 MMA sweep (tile 8 x 4, FP64 state and coefficients): the
 // launch for radius `rad` and KC chunks of 4, and its slab row pitch.

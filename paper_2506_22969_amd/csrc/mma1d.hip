@@ -75,33 +75,11 @@ __device__ inline void end_bands(const MmaArgs &p, double (*buf)[kEdgeWin][kEdge
     }
 }
 
-template <int KC, int RAD, int MODE, int PART, int BC, bool VEC>
-__global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
-    static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
-    constexpr int VPK = (MODE == kSparse) ? 8 : 4;
-    __shared__ __attribute__((aligned(16))) float lds[k1Words];
-    static_assert(sizeof(float) * k1Words >= sizeof(double) * 2 * kEdgeWin * kEdgeLanes, "end-band buffers fit");
-
-    // the workgroup after the last block recomputes the end bands
-    if (p.edge_w && (int)blockIdx.x == p.total_items) {
-        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
-        return;
-    }
-
-    // the job of this workgroup (jobs' first blocks ascend)
-    int j = 0;
-    for (int t = 1; t < p.njobs; ++t) j = (int)blockIdx.x >= p.job[t].item0 ? t : j;
-    const MmaJob g = p.job[j];
-    const int n = g.nx;
-    const int base = ((int)blockIdx.x - g.item0) * k1Block;
-    // the grid is global memory: say so, so that the loads are global ones
-    const __attribute__((address_space(1))) float *x =
-        (const __attribute__((address_space(1))) float *)static_cast<const float *>(g.in);
+// Stage x[first, first + 4112) into the skewed LDS row: 16-byte loads away
+// from the ends, element by element (zero or wrapped) near them.
+template <int BC, bool VEC>
+__device__ inline void stage_block(const __attribute__((address_space(1))) float *x, int first, int n, float *lds) {
     const int tid = threadIdx.x;
-
-    // stage x[base - 8, base + 4104): 16-byte loads away from the ends,
-    // element by element (zero or wrapped) near them
-    const int first = base - k1Halo;
     if (VEC && first >= 0 && first + k1Span <= n) {
         constexpr int NV = k1Span / 4;
         constexpr int PER = (NV + k1Threads - 1) / k1Threads;
@@ -132,6 +110,33 @@ __global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
             lds[skewed(i)] = v;
         }
     }
+}
+
+template <int KC, int RAD, int MODE, int PART, int BC, bool VEC>
+__global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
+    static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
+    constexpr int VPK = (MODE == kSparse) ? 8 : 4;
+    __shared__ __attribute__((aligned(16))) float lds[k1Words];
+    static_assert(sizeof(float) * k1Words >= sizeof(double) * 2 * kEdgeWin * kEdgeLanes, "end-band buffers fit");
+
+    // the workgroup after the last block recomputes the end bands
+    if (p.edge_w && (int)blockIdx.x == p.total_items) {
+        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
+        return;
+    }
+
+    // the job of this workgroup (jobs' first blocks ascend)
+    int j = 0;
+    for (int t = 1; t < p.njobs; ++t) j = (int)blockIdx.x >= p.job[t].item0 ? t : j;
+    const MmaJob g = p.job[j];
+    const int n = g.nx;
+    const int base = ((int)blockIdx.x - g.item0) * k1Block;
+    // the grid is global memory: say so, so that the loads are global ones
+    const __attribute__((address_space(1))) float *x =
+        (const __attribute__((address_space(1))) float *)static_cast<const float *>(g.in);
+    const int tid = threadIdx.x;
+
+    stage_block<BC, VEC>(x, base - k1Halo, n, lds);
 
     const int lane = tid & 63;
     const int wave = tid >> 6;
@@ -233,53 +238,105 @@ hipError_t launch_mma1d(MmaArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Direct 1-D sweep from the same staging: each thread sums 16 consecutive
+// outputs with FP32 FMAs from the skewed LDS row (threads 17 words apart,
+// so a wave's reads fall into distinct banks), coefficients in FP32.
+template <int RAD, int BC, bool VEC>
+__global__ __launch_bounds__(k1Threads) void k_lds1d(MmaArgs p) {
+    static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
+    constexpr int K = 2 * RAD + 1;
+    constexpr int W = 16 + 2 * RAD;
+    __shared__ __attribute__((aligned(16))) float lds[k1Words];
+    if (p.edge_w && (int)blockIdx.x == p.total_items) {
+        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
+        return;
+    }
+    int j = 0;
+    for (int t = 1; t < p.njobs; ++t) j = (int)blockIdx.x >= p.job[t].item0 ? t : j;
+    const MmaJob g = p.job[j];
+    const int n = g.nx;
+    const int base = ((int)blockIdx.x - g.item0) * k1Block;
+    const __attribute__((address_space(1))) float *x =
+        (const __attribute__((address_space(1))) float *)static_cast<const float *>(g.in);
+    stage_block<BC, VEC>(x, base - k1Halo, n, lds);
+    float w[K];
+#pragma unroll
+    for (int o = 0; o < K; ++o) w[o] = p.w[o];
+    __syncthreads();
+
+    const int tid = threadIdx.x;
+    // staged index of this thread's first input: c0 + 16 tid (c0 = 8 - RAD)
+    constexpr int c0 = k1Halo - RAD;
+    const float *src = lds + c0 + 17 * tid;
+    float v[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = src[i + ((c0 + i) >> 4)];
+    float y[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int o = 0; o < K; ++o) acc = __builtin_fmaf(w[o], v[i + o], acc);
+        y[i] = acc;
+    }
+    const int valid = min(k1Block, n - base);
+    float *out = static_cast<float *>(g.out) + base;
+    const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, valid * 4);
+    const int bw = p.edge_w ? band_width(p) : 0;
+    const int lo_end = min(bw, n) - base;
+    const int hi_start = max(n - bw, min(bw, n)) - base;
+    const bool plain = lo_end <= 0 && hi_start >= valid;
+    const int o = 16 * tid;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int oc = o + 4 * c;
+        if (VEC && plain) {
+            const u4v yv = {__float_as_uint(y[4 * c]), __float_as_uint(y[4 * c + 1]), __float_as_uint(y[4 * c + 2]),
+                            __float_as_uint(y[4 * c + 3])};
+            __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, oc < valid ? (unsigned)oc * 4u : kOob, 0, 0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int oi = oc + i;
+                const bool keep = oi < valid && oi >= lo_end && oi < hi_start;
+                __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(y[4 * c + i]), orsrc,
+                                                      keep ? (unsigned)oi * 4u : kOob, 0, 0);
+            }
+        }
+    }
+}
+
+template <int RAD>
+hipError_t launch_lds1d(MmaArgs &a, hipStream_t s) {
+    if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
+    int blocks = 0;
+    bool vec = true;
+    for (int j = 0; j < a.njobs; ++j) {
+        MmaJob &g = a.job[j];
+        if (g.nx < 1) return hipErrorInvalidValue;
+        g.item0 = blocks;
+        blocks += (g.nx + k1Block - 1) / k1Block;
+        vec = vec && g.nx % 4 == 0 && ((uintptr_t)g.in % 16) == 0 && ((uintptr_t)g.out % 16) == 0;
+    }
+    a.total_items = blocks;
+    if (a.edge_w && (a.edge_steps < 2 || a.edge_rad < 1 || a.edge_rad * a.edge_steps > k1Halo))
+        return hipErrorInvalidValue;
+    const dim3 grid(blocks + (a.edge_w ? 1 : 0)), block(k1Threads);
+    if (a.periodic) {
+        if (vec) hipLaunchKernelGGL((k_lds1d<RAD, kBcWrapN, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_lds1d<RAD, kBcWrapN, false>), grid, block, 0, s, a);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_lds1d<RAD, kBcZero, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_lds1d<RAD, kBcZero, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 template <int RAD>
 MmaLaunch pick1d(int mode, int part) {
     if (mode == kSparse) return part == kPartF16 ? &launch_mma1d<1, RAD, kSparse, kPartF16>
                                                  : &launch_mma1d<1, RAD, kSparse, kPartBF16>;
     return part == kPartF16 ? &launch_mma1d<1, RAD, kDense, kPartF16> : &launch_mma1d<1, RAD, kDense, kPartBF16>;
-}
-
-// Exact values of the points within r(S-1) of either end after S zero-halo
-// sweeps, one thread per point: the window of inputs the point depends on
-// is swept S times in FP64 in LDS, shrinking by r on each side per sweep,
-// with the points outside the grid held at zero.
-constexpr int kEdge1Threads = 64;
-constexpr int kEdge1Win = 2 * k1Halo + 1;
-
-__global__ __launch_bounds__(kEdge1Threads) void k_edge1d(EdgeArgs a) {
-    __shared__ double buf[2][kEdge1Win][kEdge1Threads];
-    const int t = blockIdx.x * kEdge1Threads + threadIdx.x;
-    if (t >= a.total) return;
-    int j = 0;
-    for (int i = 1; i < a.njobs; ++i) j = t >= a.job[i].point0 ? i : j;
-    const EdgeJob g = a.job[j];
-    const int n = g.nx;
-    const int R = a.rad * a.steps;            // composed radius
-    const int b = a.rad * (a.steps - 1);      // band width
-    const int lo_count = min(b, n);
-    const int i = t - g.point0;
-    const int pt = i < lo_count ? i : n - (i - lo_count) - 1;
-    const int L = 2 * R + 1;
-    const int k = 2 * a.rad + 1;
-    double(*cur)[kEdge1Threads] = buf[0];
-    double(*nxt)[kEdge1Threads] = buf[1];
-    for (int w = 0; w < L; ++w) {
-        const int gi = pt - R + w;
-        cur[w][threadIdx.x] = (gi >= 0 && gi < n) ? (double)g.in[gi] : 0.0;
-    }
-    for (int s = 1; s <= a.steps; ++s) {
-        for (int w = s * a.rad; w < L - s * a.rad; ++w) {
-            const int gi = pt - R + w;
-            double acc = 0.0;
-            for (int o = 0; o < k; ++o) acc += a.w[o] * cur[w + o - a.rad][threadIdx.x];
-            nxt[w][threadIdx.x] = (gi >= 0 && gi < n) ? acc : 0.0;
-        }
-        double(*tmp)[kEdge1Threads] = cur;
-        cur = nxt;
-        nxt = tmp;
-    }
-    g.out[pt] = (float)cur[R][threadIdx.x];
 }
 
 }  // namespace
@@ -298,21 +355,18 @@ MmaLaunch find_mma1d(int rad, int mode, int part) {
     }
 }
 
-hipError_t launch_edge1d(EdgeArgs &a, hipStream_t s) {
-    if (a.njobs < 1 || a.njobs > kMaxJobs || a.steps < 2 || a.rad < 1 || a.rad * a.steps > k1Halo)
-        return hipErrorInvalidValue;
-    const int b = a.rad * (a.steps - 1);
-    int total = 0;
-    for (int j = 0; j < a.njobs; ++j) {
-        EdgeJob &g = a.job[j];
-        if (g.nx < 1 || g.ny != 1) return hipErrorInvalidValue;
-        g.point0 = total;
-        total += min(2 * b, g.nx);
+MmaLaunch find_lds_direct1d(int rad) {
+    switch (rad) {
+        case 1: return &launch_lds1d<1>;
+        case 2: return &launch_lds1d<2>;
+        case 3: return &launch_lds1d<3>;
+        case 4: return &launch_lds1d<4>;
+        case 5: return &launch_lds1d<5>;
+        case 6: return &launch_lds1d<6>;
+        case 7: return &launch_lds1d<7>;
+        case 8: return &launch_lds1d<8>;
+        default: return nullptr;
     }
-    a.total = total;
-    if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge1d, dim3((total + kEdge1Threads - 1) / kEdge1Threads), dim3(kEdge1Threads), 0, s, a);
-    return hipGetLastError();
 }
 
 }  // namespace ss

@@ -552,15 +552,18 @@ ss_status plan_mma1d(ss_plan_ *p, int engine) {
 
 ss_status plan_direct(ss_plan_ *p) {
     const bool f64 = p->dtype == SS_F64;
-    // 2-D FP32-state or plane grids and 3-D FP32-state grids run on the
-    // LDS-pipelined kernels (planes need rows of a multiple of 8 values);
-    // FP64, 1-D and the rest on the plain one
+    // 2-D FP32-state or plane grids, 3-D and 1-D FP32-state grids run on the
+    // LDS-staged kernels (planes need rows of a multiple of 8 values);
+    // FP64, 1-D planes and the rest on the plain one
     const int state = mma_state(p->dtype);
     MmaLaunch lds = nullptr;
     if (!f64 && p->ndim == 2 && (state != kStatePlanes || p->dims[2] % 8 == 0) && slab_offsets_fit(p))
         lds = find_lds_direct2d(p->rad, state);
     if (!f64 && p->ndim == 3 && state == kStateF32 && slab_offsets_fit(p)) lds = find_lds_direct3d(p->rad);
+    if (!f64 && p->ndim == 1 && state == kStateF32) lds = find_lds_direct1d(p->rad);
     if (!lds && p->rad > kDirectMaxRad) return SS_E_UNSUPPORTED;
+    // a fused zero-halo 1-D sweep needs the staged kernel's end-band workgroup
+    if (!lds && p->ndim == 1 && p->edge_rad) return SS_E_UNSUPPORTED;
     const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
     const size_t o_zero = (wbytes + 255) & ~(size_t)255;
     std::vector<uint8_t> blob(o_zero + 1024, 0);
@@ -803,7 +806,7 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
     for (int j = 0; j < n; ++j)
         ea.job[j] = EdgeJob{static_cast<const float *>(in[j]), static_cast<float *>(out[j]), (int)dims[j][1],
                             (int)dims[j][2], 0};
-    return p->ndim == 1 ? launch_edge1d(ea, s) : launch_edge2d(ea, s);
+    return launch_edge2d(ea, s);
 }
 
 hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s) {

@@ -121,17 +121,12 @@ def test_1d_fused(engine, radius, fuse, n, boundary):
     w, _ = synthetic.random_coeffs("box", radius, 1, seed=5, grid_shape=(4096,))
     x0 = synthetic.grid_f32((n,), seed=3)
     steps = 2 * fuse + 1
-    if engine == "direct" and radius * fuse > 6:
-        # the direct kernels stop at radius 6: refused at plan time
-        with pytest.raises(native.SparStencilError):
-            native.Plan("box", radius, w, (n,), "f32_split_f16", boundary=boundary, fuse_steps=fuse, engine=engine)
-        return
     with native.Plan("box", radius, w, (n,), "f32_split_f16", boundary=boundary, fuse_steps=fuse,
                      engine=engine) as p:
         info = p.info
         assert info["fuse_steps"] == fuse and info["k"] == 2 * radius * fuse + 1
-        # the matrix kernels recompute the end bands in the sweep's own launch
-        assert info["launches_per_sweep"] == (2 if boundary == "zero" and engine == "direct" else 1)
+        # every 1-D kernel recomputes the end bands in the sweep's own launch
+        assert info["launches_per_sweep"] == 1
         got = run_plan(p, x0, steps)
     ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=boundary == "periodic")
     err = normwise_err(got, ref)

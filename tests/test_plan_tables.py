@@ -236,14 +236,14 @@ def test_1d_kernel_order_is_a_valid_layout(radius, fuse, engine):
 
 def test_1d_zero_halo_fusion_scope():
     """1-D zero-halo fusion: any S with r*S <= 8 (the staged halo), the two
-    end bands recomputed by one more workgroup of the matrix kernel's launch
-    (a second launch on the direct engine); beyond that it is rejected."""
+    end bands recomputed by one more workgroup of the sweep's launch (matrix
+    and direct kernels alike); beyond that it is rejected."""
     w1, _ = synthetic.random_coeffs("box", 1, 1, seed=3, grid_shape=(4096,))
     w3, _ = synthetic.random_coeffs("box", 3, 1, seed=3, grid_shape=(4096,))
     with native.Plan("box", 1, w1, (1000,), "f32_split_f16", fuse_steps=8, host_only=True) as p:
         assert p.info["launches_per_sweep"] == 1 and p.info["k"] == 17
     with native.Plan("box", 1, w1, (1000,), "f32_split_f16", fuse_steps=3, engine="direct", host_only=True) as p:
-        assert p.info["launches_per_sweep"] == 2
+        assert p.info["launches_per_sweep"] == 1 and p.info["engine_name"] == "direct"
     with pytest.raises(native.SparStencilError):
         native.Plan("box", 3, w3, (1000,), "f32_split_f16", fuse_steps=3, host_only=True)
     with native.Plan("box", 3, w3, (1000,), "f32_split_bf16", host_only=True) as p:
