@@ -13,6 +13,11 @@
 // 17n words after tile 0, so the sixteen B columns of a gather fall into
 // different banks.  The gather offset of patch column p is then
 // p + ((c0 + p) >> 4) for every tile, with c0 = 8 - radius.
+//
+// The direct engine's 1-D kernel (k_lds1d) shares the staging.  A launch of
+// S fused sweeps on a zero-halo grid has one more workgroup, which
+// recomputes the points within r(S-1) of either end exactly while the other
+// workgroups leave them unwritten.
 #include "mma2d_impl.hpp"
 
 namespace ss {
