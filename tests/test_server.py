@@ -68,6 +68,7 @@ def test_server_mix_matches_run_alone():
         (w9, (64, 264), "split_bf16", "smfmac", "periodic", 3),
         (w9, (96, 264), "split_bf16", "smfmac", "periodic", 6),
         ("1d", (100003,), "f32_split_f16", "smfmac", "zero", 7, 3),
+        ("1d", (77777,), "f32_split_f16", "smfmac", "zero", 9, 3),   # batches with the one above
         ("1d", (4096,), "f32_split_bf16", "mfma", "periodic", 5),
     ]
     plans, jobs = [], []
