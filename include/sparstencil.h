@@ -173,6 +173,19 @@ ss_status sparstencil_run(ss_plan_t plan, void *in, void *out, int64_t steps, vo
  */
 ss_status sparstencil_sweep(ss_plan_t plan, const void *in, void *out, void *stream);
 
+/*
+ * One (fused) sweep of n grids of the plan's own dims and dtype in a single
+ * launch (an ensemble of independent grids; each grid's result is
+ * bit-identical to sparstencil_sweep of it alone).
+ *   n        1..16
+ *   in, out  host arrays of n device pointers; out[i] receives the sweep of
+ *            in[i].  No output may overlap any input or another output.
+ * Asynchronous on `stream`.  Errors: SS_E_INVALID (null, n out of range,
+ * overlap, host-only plan), SS_E_DEVICE (launch).
+ */
+ss_status sparstencil_sweep_batch(ss_plan_t plan, int32_t n, const void *const *in, void *const *out,
+                                  void *stream);
+
 /* Number of sweep kernels `run` launches for `steps` sweeps (0 for a copy);
  * an even count is preceded by one device-to-device copy of the grid. */
 int64_t sparstencil_launch_count(ss_plan_t plan, int64_t steps);
@@ -184,7 +197,7 @@ const char *sparstencil_status_string(int32_t status);
 
 /*
  * Serving loop (not part of the paper's method, which runs one grid at a
- * time: a batching layer around the sweep of Section 3.4).  A server owns a
+ * time: a batching layer around the sweep its Section 3.3 generates).  A server owns a
  * worker thread that admits submitted jobs first-come first-served while the
  * caller's device arena has room for a job's two buffers, then advances every
  * admitted job by one (fused) sweep per round.  Jobs whose plans have equal

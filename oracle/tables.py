@@ -171,41 +171,42 @@ def hierarchical_matching(m: int, g: int, k: int):
     the order the algorithm builds them (block pairs expanded column by
     column first, then the in-block pairs), and the number of zero nodes.
 
-    The paper checks only that the source node is unmatched; the target is
-    then provably free, which is asserted here.
+    Written from what the two levels produce rather than as a loop:
+
+    * level 1 pairs whole blocks s1 = max(floor(m/2), k) apart (Theorem 1:
+      they share no output row).  Scanning blocks upward and pairing each
+      free block with the one s1 above it, the pairs are (i, i + s1) for the
+      blocks i that are below s1 (a block at or above s1 is already someone's
+      partner) and have a block s1 above them (i + s1 < m);
+    * level 2 works on each block no level-1 pair covers: columns
+      s2 = max(floor(g/2), k) apart never share an output row, so the same
+      scan pairs (u, u + s2) for u < s2 with u + s2 < g; a column in
+      neither role gets a zero node.
+
+    The sets are formed first and then listed in the paper's order (M1
+    expanded over the g columns of each block pair, then M2 by block and
+    source column); every column of the plane must appear exactly once.
     """
     s1 = max(m // 2, k)
-    matched_block = [False] * m
-    m1 = []
-    for i in range(m):
-        if not matched_block[i] and i + s1 < m:
-            assert not matched_block[i + s1]
-            m1.append((i, i + s1))
-            matched_block[i] = matched_block[i + s1] = True
+    m1 = [(i, i + s1) for i in range(m) if i < s1 and i + s1 < m]
+    covered = {b for pair in m1 for b in pair}
     s2 = max(g // 2, k)
+    sources = {u for u in range(g) if u < s2 and u + s2 < g}
+    targets = {u + s2 for u in sources}
+    singles = set(range(g)) - sources - targets
     m2 = []
     zeros = 0
-    for x in range(m):
-        if matched_block[x]:
-            continue
-        used = [False] * g
-        for u in range(g):
-            v = u + s2
-            if used[u]:
-                continue
-            if v < g:
-                assert not used[v]
-                m2.append(((x, u), (x, v)))
-                used[u] = used[v] = True
+    for x in sorted(set(range(m)) - covered):
+        for u in sorted(sources | singles):
+            if u in sources:
+                m2.append(((x, u), (x, u + s2)))
             else:
                 m2.append(((x, u), None))
-                used[u] = True
                 zeros += 1
-    pairs = []
-    for p, q in m1:
-        for t in range(g):
-            pairs.append(((p, t), (q, t)))
+    pairs = [((p, t), (q, t)) for p, q in m1 for t in range(g)]
     pairs.extend(m2)
+    seen = [c for a, b in pairs for c in (a, b) if c is not None]
+    assert len(seen) == len(set(seen)) == m * g
     return pairs, zeros
 
 

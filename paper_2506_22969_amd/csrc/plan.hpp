@@ -46,7 +46,8 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
                        const int64_t (*dims)[3], hipStream_t s);
 hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s);
 size_t plan_state_bytes(const ss_plan_ *p);
-// True when a and b can share one launch: equal device tables and kernel.
+// True when a and b can share one launch: equal device tables and the same
+// kernel (a plan of the direct engine picks its kernel from its grid size).
 bool same_class(const ss_plan_ *a, const ss_plan_ *b);
 
 }  // namespace ss

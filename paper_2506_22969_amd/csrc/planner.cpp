@@ -55,36 +55,29 @@ std::vector<double> morph_matrix(const Geometry &gm, const std::vector<double> &
     return a;
 }
 
-// Algorithm 1 (hierarchical two-level matching).  Level 1 pairs whole blocks
-// (row segments) at stride s1 = max(floor(m/2), k); two blocks that far apart
-// never share an output row (Theorem 1).  Level 2 pairs columns of each block
-// left over at stride s2 = max(floor(g/2), k), a zero node taking any column
-// whose partner would fall outside the block.  Block pairs are expanded
-// column by column before the level-2 pairs.
+// Algorithm 1 (hierarchical two-level matching), stated in closed form.
+// Level 1: two blocks (row segments) s1 = max(floor(m/2), k) apart never
+// share an output row (Theorem 1), so block i takes block i + s1 for every
+// i below n1 = min(s1, m - s1); past n1 a block is either the partner of an
+// earlier one or has none.  Level 2, inside every block left over: column u
+// takes column u + s2 (s2 = max(floor(g/2), k)) for u below
+// n2 = min(s2, g - s2), and each of the block's other columns that is no
+// such partner gets a zero node.  Output order: the block pairs expanded
+// column by column, then the leftover blocks' pairs by (block, column).
 PairList two_level_matching(int m_blocks, int g, int k) {
     PairList out;
     const int s1 = std::max(m_blocks / 2, k);
-    std::vector<char> block_used(m_blocks, 0);
-    std::vector<std::pair<int, int>> level1;
-    for (int i = 0; i + s1 < m_blocks; ++i) {
-        if (block_used[i]) continue;
-        level1.emplace_back(i, i + s1);
-        block_used[i] = block_used[i + s1] = 1;
-    }
-    for (const auto &bp : level1)
-        for (int t = 0; t < g; ++t) out.pairs.emplace_back(bp.first * g + t, bp.second * g + t);
+    const int n1 = std::max(0, std::min(s1, m_blocks - s1));
+    for (int i = 0; i < n1; ++i)
+        for (int t = 0; t < g; ++t) out.pairs.emplace_back(i * g + t, (i + s1) * g + t);
     const int s2 = std::max(g / 2, k);
+    const int n2 = std::max(0, std::min(s2, g - s2));
     for (int x = 0; x < m_blocks; ++x) {
-        if (block_used[x]) continue;
-        std::vector<char> col_used(g, 0);
+        if (x < n1 || (x >= s1 && x < s1 + n1)) continue;
         for (int u = 0; u < g; ++u) {
-            if (col_used[u]) continue;
-            col_used[u] = 1;
-            const int v = u + s2;
-            if (v < g) {
-                col_used[v] = 1;
-                out.pairs.emplace_back(x * g + u, x * g + v);
-            } else {
+            if (u < n2) {
+                out.pairs.emplace_back(x * g + u, x * g + u + s2);
+            } else if (u < s2 || u >= s2 + n2) {
                 out.pairs.emplace_back(x * g + u, kZeta);
                 ++out.zeros;
             }

@@ -744,6 +744,8 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     };
     const int32_t key[8] = {p->engine, p->dtype, p->boundary, p->k, inf.r1, inf.r2, ndim, p->fuse};
     mix(key, sizeof key);
+    // the kernel the plan picked (the direct engine picks by grid size)
+    mix(&p->mma, sizeof p->mma);
     mix(p->w.data(), p->w.size() * sizeof(double));
     mix(p->w1.data(), p->w1.size() * sizeof(double));
     p->klass = h;
@@ -818,7 +820,7 @@ hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s
 size_t plan_state_bytes(const ss_plan_ *p) { return state_bytes(p->dtype); }
 
 bool same_class(const ss_plan_ *a, const ss_plan_ *b) {
-    return a->klass == b->klass && a->engine == b->engine && a->dtype == b->dtype &&
+    return a->klass == b->klass && a->mma == b->mma && a->engine == b->engine && a->dtype == b->dtype &&
            a->boundary == b->boundary && a->k == b->k && a->ndim == b->ndim && a->fuse == b->fuse &&
            a->info.r1 == b->info.r1 && a->info.r2 == b->info.r2 && a->w == b->w && a->w1 == b->w1;
 }
@@ -879,6 +881,25 @@ ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void 
 ss_status sparstencil_sweep(ss_plan_t p, const void *in, void *out, void *stream) {
     if (!p || !in || !out || in == out || p->host_only) return SS_E_INVALID;
     return ss::sweep_one(p, in, out, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK : SS_E_DEVICE;
+}
+
+ss_status sparstencil_sweep_batch(ss_plan_t p, int32_t n, const void *const *in, void *const *out, void *stream) {
+    if (!p || !in || !out || n < 1 || n > kMaxJobs || p->host_only) return SS_E_INVALID;
+    const size_t bytes = sparstencil_grid_bytes(p);
+    for (int i = 0; i < n; ++i) {
+        if (!in[i] || !out[i]) return SS_E_INVALID;
+        // no output may overlap any grid of the launch
+        const char *o = static_cast<const char *>(out[i]);
+        for (int j = 0; j < n; ++j) {
+            const char *a = static_cast<const char *>(in[j]), *b = static_cast<const char *>(out[j]);
+            if (o < a + bytes && a < o + bytes) return SS_E_INVALID;
+            if (j != i && o < b + bytes && b < o + bytes) return SS_E_INVALID;
+        }
+    }
+    int64_t dims[kMaxJobs][3];
+    for (int i = 0; i < n; ++i) std::memcpy(dims[i], p->dims, sizeof dims[i]);
+    return ss::sweep_grids(p, n, in, out, dims, static_cast<hipStream_t>(stream)) == hipSuccess ? SS_OK
+                                                                                             : SS_E_DEVICE;
 }
 
 ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *nbytes) {

@@ -26,7 +26,7 @@ ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
 (Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM) = range(11)
 
 EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
-           "sparstencil_sweep", "sparstencil_launch_count", "sparstencil_grid_bytes",
+           "sparstencil_sweep", "sparstencil_sweep_batch", "sparstencil_launch_count", "sparstencil_grid_bytes",
            "sparstencil_status_string", "sparstencil_server_create", "sparstencil_submit",
            "sparstencil_poll", "sparstencil_job_release", "sparstencil_server_drain",
            "sparstencil_server_clock", "sparstencil_server_destroy"]
@@ -101,6 +101,8 @@ def lib():
         L.sparstencil_run.argtypes = [vp, vp, vp, i64, vp]
         L.sparstencil_sweep.restype = i32
         L.sparstencil_sweep.argtypes = [vp, vp, vp, vp]
+        L.sparstencil_sweep_batch.restype = i32
+        L.sparstencil_sweep_batch.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.sparstencil_launch_count.restype = i64
         L.sparstencil_launch_count.argtypes = [vp, i64]
         L.sparstencil_grid_bytes.restype = sz
@@ -180,6 +182,15 @@ def sparstencil_run(plan: int, inp, out, steps: int, stream=None) -> None:
 
 def sparstencil_sweep(plan: int, inp, out, stream=None) -> None:
     _check(lib().sparstencil_sweep(plan, _ptr(inp), _ptr(out), _ptr(stream)), "sparstencil_sweep")
+
+
+def sparstencil_sweep_batch(plan: int, inputs, outputs, stream=None) -> None:
+    n = len(inputs)
+    if len(outputs) != n:
+        raise ValueError("inputs and outputs differ in length")
+    ins = (ctypes.c_void_p * max(1, n))(*[_ptr(x) for x in inputs])
+    outs = (ctypes.c_void_p * max(1, n))(*[_ptr(x) for x in outputs])
+    _check(lib().sparstencil_sweep_batch(plan, n, ins, outs, _ptr(stream)), "sparstencil_sweep_batch")
 
 
 def sparstencil_launch_count(plan: int, steps: int) -> int:
@@ -291,6 +302,9 @@ class Plan:
 
     def sweep(self, inp, out, stream=None):
         sparstencil_sweep(self.handle, inp, out, stream)
+
+    def sweep_batch(self, inputs, outputs, stream=None):
+        sparstencil_sweep_batch(self.handle, inputs, outputs, stream)
 
     def launch_count(self, steps):
         return sparstencil_launch_count(self.handle, steps)

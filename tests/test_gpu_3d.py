@@ -14,7 +14,7 @@ import synthetic
 from oracle import direct as oracle_direct
 from oracle.sampling import cone_sample, sample_points3
 
-from .helpers import normwise_err, split_step_bound
+from .helpers import STATED_SPLIT, normwise_err, split_step_bound
 
 torch = pytest.importorskip("torch")
 native = pytest.importorskip("paper_2506_22969_amd.native")
@@ -130,3 +130,5 @@ def test_3d_c4_full_size_sampled(shape):
     tol = tol_for(info, w, steps, "f32_split_f16")
     print(f"C4 {shape} sampled err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+    # the split path's stated 1e-6 (measured 2e-7 Heat-3D, 6e-7 Box-3D27P)
+    assert err <= STATED_SPLIT

@@ -1,10 +1,13 @@
 """GPU parity: libsparstencil's HIP engines against the FP64 oracle, through
 the C ABI, on seeded synthetic grids.
 
-Tolerances (normwise relative error after T sweeps): each
-split-precision sweep is bounded by split_step_bound(fmt, n_mma) * sum|c|
-relative to the largest state value; the tests allow T times that bound.
-The direct FP32 engine gets T * (P + 1) * 2^-24 * sum|c|, FP64 1e-13.
+Tolerances (normwise relative error after T sweeps): each split-precision
+sweep is bounded by split_step_bound(fmt, n_mma) * sum|c| relative to the
+largest state value; the tests allow T times that bound.  The direct FP32
+engine gets T * (P + 1) * 2^-24 * sum|c|, FP64 1e-13.  Binary16-split and
+FP32 results are also held to the stated bounds (STATED_F32 = 1e-5, and
+STATED_SPLIT = 1e-6 for the fused workloads that reach it), which on the
+100-sweep workloads sit a few times above the measured errors.
 """
 import numpy as np
 import pytest
@@ -12,7 +15,8 @@ import pytest
 import synthetic
 from oracle import direct as oracle_direct
 
-from .helpers import cone_sample, normwise_err, sample_points, split_step_bound
+from .helpers import (STATED_F32, STATED_SPLIT, apriori_bound, cone_sample, normwise_err, sample_points,
+                      split_step_bound)
 
 torch = pytest.importorskip("torch")
 native = pytest.importorskip("paper_2506_22969_amd.native")
@@ -69,6 +73,7 @@ def test_box9_f16_split_small(engine, dims, boundary):
     tol = tol_for(info, w, steps, "f32_split_f16")
     print(f"engine={engine} dims={dims} bc={boundary} err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+    assert err <= STATED_F32
 
 
 @pytest.mark.parametrize("engine", ["smfmac", "mfma"])
@@ -193,6 +198,8 @@ def test_box9_full_size_sampled():
     tol = tol_for(info, w, steps, "f32_split_f16")
     print(f"full-size sampled err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+    # stated bound of the FP32-state split path (measured about 2.7e-6)
+    assert err <= STATED_F32
 
 
 @pytest.mark.parametrize("fuse", [2, 3])
@@ -219,6 +226,9 @@ def test_box9_full_size_fused_sampled(fuse):
     tol = (steps // fuse) * b * ss + (steps % fuse) * b * s1
     print(f"full-size fused S={fuse} sampled err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+    # three fused sweeps per launch reach the split path's 1e-6 (measured
+    # about 2e-7); two land at about 7e-7, held to 3e-6 and the FP32 bound
+    assert err <= (STATED_SPLIT if fuse == 3 else 3e-6)
 
 
 FUSED_ZERO = [("box", (64, 64)), ("star", (300, 264)), ("box", (37, 41)), ("box", (3, 5)), ("box", (520, 1030))]
@@ -251,3 +261,78 @@ def test_fusion_with_zero_halo(engine, shape, dims, fuse, steps):
         tol = fused * b * ss + rest * b * s1
     print(f"engine={engine} {shape} dims={dims} S={fuse} steps={steps} err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+
+
+MULTI_ITEM = [  # (dims, boundary, fuse, steps): >= 4 work items per workgroup on 256 CUs
+    ((2080, 4100), "zero", 1, 6),      # 17 x 65 items, a ragged last band and row block
+    ((2080, 4100), "zero", 3, 7),      # two fused launches (plus edge bands), one unfused
+    ((2048, 4098), "periodic", 1, 5),  # rows not a multiple of 4 values: 4-byte transfers
+    ((2050, 4096), "periodic", 3, 6),  # periodic composed stencil, ragged rows
+]
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma"])
+@pytest.mark.parametrize("dims,boundary,fuse,steps", MULTI_ITEM)
+def test_multi_item_full_grid(engine, dims, boundary, fuse, steps):
+    """The persistent FP32 kernel in its steady state: at least four work
+    items per workgroup, so the slab rotation, the items fetched ahead and
+    the XCD-interleaved ranges all run, checked point by point against the
+    oracle on the whole grid."""
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
+    x0 = synthetic.grid_f32(dims, seed=11)
+    with native.Plan("box", 1, w, dims, "f32_split_f16", boundary=boundary, fuse_steps=fuse, engine=engine) as p:
+        info = p.info
+        assert info["engine_name"] == engine and info["fuse_steps"] == fuse
+        got = run_plan(p, x0, steps)
+    items = -(-dims[1] // 256) * -(-dims[0] // 32)
+    assert items >= 4 * 256
+    ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=(boundary == "periodic"))
+    err = normwise_err(got, ref)
+    tol = apriori_bound(info, w, steps, "f32_split_f16")
+    print(f"{engine} {dims} {boundary} S={fuse} items={items} err={err:.3e} tol={tol:.3e}")
+    assert err <= tol
+    assert err <= STATED_F32
+
+
+@pytest.mark.parametrize("engine,dtype,fuse", [("smfmac", "f32_split_f16", 1), ("smfmac", "f32_split_f16", 3),
+                                               ("mfma", "f32_split_bf16", 1), ("direct", "f32", 1),
+                                               ("smfmac", "split_bf16", 1)])
+def test_sweep_batch_exceeds_cus(engine, dtype, fuse):
+    """One launch over 16 grids whose work items together (16 x 165) exceed
+    four per compute unit: every grid's result equals its sweep alone, bit
+    for bit, and the oracle's within the bound."""
+    from .helpers import planes_value
+    dims = (1056, 1100) if dtype != "split_bf16" else (1056, 1104)
+    boundary = "zero"
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=dims)
+    n = 16
+    if dtype == "split_bf16":
+        hosts = [synthetic.grid_bf16_planes(dims, seed=40 + i) for i in range(n)]
+        ins = [torch.from_numpy(h.view(np.int16)).to(DEV) for h in hosts]
+        starts = [planes_value(h) for h in hosts]
+    else:
+        hosts = [synthetic.grid_f32(dims, seed=40 + i) for i in range(n)]
+        ins = [torch.from_numpy(h).to(DEV) for h in hosts]
+        starts = [h.astype(np.float64) for h in hosts]
+    outs = [torch.empty_like(x) for x in ins]
+    with native.Plan("box", 1, w, dims, dtype, boundary=boundary, fuse_steps=fuse, engine=engine) as p:
+        info = p.info
+        assert info["engine_name"] == engine
+        p.sweep_batch(ins, outs, stream())
+        alone = torch.empty_like(ins[0])
+        torch.cuda.synchronize()
+        for i in range(n):
+            p.sweep(ins[i], alone, stream())
+            torch.cuda.synchronize()
+            assert torch.equal(alone, outs[i]), f"grid {i} differs from its sweep alone"
+        with pytest.raises(native.SparStencilError):
+            p.sweep_batch([ins[0], ins[1]], [outs[0], outs[0]], stream())
+        with pytest.raises(native.SparStencilError):
+            p.sweep_batch([ins[0]], [ins[0]], stream())
+    for i in range(n):
+        got = outs[i].cpu().numpy()
+        got = planes_value(got.view(np.uint16)) if dtype == "split_bf16" else got.astype(np.float64)
+        ref = oracle_direct.run(starts[i], w, fuse, periodic=False)
+        err = normwise_err(got, ref)
+        tol = apriori_bound(info, w, fuse, dtype)
+        assert err <= tol, (i, err, tol)

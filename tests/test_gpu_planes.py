@@ -152,3 +152,8 @@ def test_planes_c3_full_size_sampled(shape):
     tol = tol_planes(info, w, steps, 2)
     print(f"C3 {shape} sampled err={err:.3e} tol={tol:.3e}")
     assert err <= tol
+    # the planes state re-rounds to 16 significant bits every launch, so no
+    # stated 1e-6 applies; an empirical ceiling about 3x the measured
+    # 1.6e-5 (Star-13) and 2.9e-5 (Box-49) catches a regression the a-priori
+    # bound would let through
+    assert err <= 1e-4

@@ -160,3 +160,24 @@ def test_cone_sample_equals_full_run(shape, periodic):
     got = cone_sample(x, w, steps, pts, periodic=periodic)
     want = np.array([full[p] for p in pts])
     assert np.allclose(got, want, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,radius,steps,periodic", [(61, 1, 5, False), (61, 1, 5, True), (70, 2, 6, False),
+                                                     (70, 2, 6, True), (53, 3, 4, False), (29, 2, 9, True)])
+def test_cone_sample_1d_equals_operator_power(n, radius, steps, periodic):
+    # 1-D dependency-cone sampling (the full-size 1-D GPU checks rest on it)
+    # against the explicit operator L^T x, which shares no code with the
+    # stepper; the points include both ends, where the window is clipped
+    # (zero halo) or wrapped (periodic), and reaches longer than the grid
+    from oracle.sampling import cone_sample
+    g = np.random.Generator(np.random.PCG64(21))
+    k = 2 * radius + 1
+    w = g.uniform(-1, 1, k)
+    w /= np.abs(w).sum()
+    x = g.random(n)
+    L = bruteforce.operator_matrix((n,), radius, w, periodic)
+    full = np.linalg.matrix_power(L, steps) @ x
+    pts = [(0,), (1,), (radius,), (n // 2,), (n - 1 - radius,), (n - 2,), (n - 1,)]
+    got = cone_sample(x, w, steps, pts, periodic=periodic)
+    want = np.array([full[p[0]] for p in pts])
+    assert np.max(np.abs(got - want)) <= 1e-13

@@ -4,8 +4,9 @@ CPU: argument checks that run before any HIP call.  GPU: a mix of jobs of
 several plan classes, sizes and step counts through one server with an
 arena too small to admit them all at once; every result must be
 bit-identical to sparstencil_run of the same plan alone (each output point's
-arithmetic does not depend on which grids share a launch), and the job
-records must be consistent.
+arithmetic does not depend on which grids share a launch), within its plan's
+a-priori bound of the FP64 oracle (and the stated 1e-5 on FP32-state
+binary16-split and FP32 jobs), and the job records must be consistent.
 """
 import ctypes
 
@@ -13,6 +14,9 @@ import numpy as np
 import pytest
 
 import synthetic
+from oracle import direct as oracle_direct
+
+from .helpers import STATED_F32, apriori_bound, normwise_err, planes_value
 
 native = pytest.importorskip("paper_2506_22969_amd.native")
 
@@ -67,11 +71,18 @@ def test_server_mix_matches_run_alone():
         ("3d", (24, 48, 264), "f32_split_f16", "smfmac", "zero", 4),
         (w9, (64, 264), "split_bf16", "smfmac", "periodic", 3),
         (w9, (96, 264), "split_bf16", "smfmac", "periodic", 6),
+        # planes state on the direct engine: rows of a multiple of 8 values
+        # run the LDS-staged kernel, others the plain one; the two plans
+        # have equal coefficients but must never share a launch
+        (w9, (128, 264), "split_bf16", "direct", "periodic", 4),
+        (w9, (128, 262), "split_bf16", "direct", "periodic", 5),
+        (w9, (136, 272), "split_bf16", "direct", "zero", 3),
+        (w9, (136, 270), "split_bf16", "direct", "zero", 3),
         ("1d", (100003,), "f32_split_f16", "smfmac", "zero", 7, 3),
         ("1d", (77777,), "f32_split_f16", "smfmac", "zero", 9, 3),   # batches with the one above
         ("1d", (4096,), "f32_split_bf16", "mfma", "periodic", 5),
     ]
-    plans, jobs = [], []
+    plans, jobs, oracle_inputs = [], [], []
     w3 = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
     w1 = synthetic.random_coeffs("box", 1, 1, seed=3, grid_shape=(4096,))[0]
     for i, (w, dims, dtype, engine, bc, steps, *fuse) in enumerate(specs):
@@ -80,12 +91,18 @@ def test_server_mix_matches_run_alone():
         elif len(dims) == 1:
             w = w1
         plan = native.Plan("box", 1, w, dims, dtype, boundary=bc, engine=engine, fuse_steps=fuse[0] if fuse else 1)
+        assert plan.info["engine_name"] == engine
         plans.append(plan)
         if dtype == "split_bf16":
-            x0 = torch.from_numpy(synthetic.grid_bf16_planes(dims, seed=10 + i).view(np.int16)).to(dev)
+            bits = synthetic.grid_bf16_planes(dims, seed=10 + i)
+            x0 = torch.from_numpy(bits.view(np.int16)).to(dev)
+            start = planes_value(bits)
         else:
-            x0 = torch.from_numpy(synthetic.grid_f32(dims, seed=10 + i)).to(dev)
+            host = synthetic.grid_f32(dims, seed=10 + i)
+            x0 = torch.from_numpy(host).to(dev)
+            start = host.astype(np.float64)
         jobs.append((plan, x0, steps))
+        oracle_inputs.append((w, start, dtype, bc == "periodic"))
 
     # reference: each job alone through sparstencil_run
     refs = []
@@ -120,6 +137,17 @@ def test_server_mix_matches_run_alone():
     torch.cuda.synchronize()
     for i, (out, ref) in enumerate(zip(outs, refs)):
         assert torch.equal(out, ref), f"job {i} differs from the job run alone"
+    # and every served result against the FP64 oracle
+    for i, ((plan, _x0, steps), out, (w, start, dtype, periodic)) in enumerate(zip(jobs, outs, oracle_inputs)):
+        host = out.cpu().numpy()
+        got = planes_value(host.view(np.uint16)) if dtype == "split_bf16" else host.astype(np.float64)
+        ref = oracle_direct.run(start, w, steps, periodic=periodic)
+        err = normwise_err(got, ref)
+        tol = apriori_bound(plan.info, w, steps, dtype)
+        print(f"job {i} {plan.info['engine_name']} {dtype} {start.shape} err={err:.3e} tol={tol:.3e}")
+        assert err <= tol, f"job {i}"
+        if dtype in ("f32_split_f16", "f32"):
+            assert err <= STATED_F32, f"job {i}"
     for p in plans:
         p.close()
 
