@@ -46,10 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep-loop", type=int, default=40, help="sweeps timed for the roofline")
-    ap.add_argument("--serve-jobs", type=int, default=200,
+    ap.add_argument("--serve-jobs", type=int, default=2000,
                     help="jobs of the serving-mix leg (0 skips it)")
-    ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="Poisson arrival rate as a fraction of the measured batch capacity")
+    ap.add_argument("--serve-loads", default="0.5,0.7,0.9",
+                    help="Poisson arrival rates as fractions of the measured batch capacity")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
     ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p", "heat1d3p", "1d5p"],
@@ -124,29 +124,50 @@ def sweep_roofline(torch, plan, x0_dev, stream, n):
     return e0.elapsed_time(e1) / n
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x0: np.ndarray, w: np.ndarray, gpu_out: np.ndarray, budget_s: float):
     """The FP64 oracle on the host cores: full-grid sweeps for about budget_s
-    seconds (throughput), then sampled outputs of the 100-sweep run through
-    their dependency cones (error of the GPU result)."""
+    seconds on all the threads OpenMP gives it (throughput), a third as long
+    on one thread, then sampled outputs of the 100-sweep run through their
+    dependency cones (error of the GPU result)."""
     from oracle import direct as oracle_direct
     from oracle.sampling import cone_sample, sample_points
 
     xd = x0.astype(np.float64)
-    t0 = time.perf_counter()
-    oracle_direct.run(xd, w, 1)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(budget_s / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    oracle_direct.run(xd, w, n)
-    dt = time.perf_counter() - t0
+
+    def rate(seconds, nthreads):
+        t0 = time.perf_counter()
+        oracle_direct.run(xd, w, 1, nthreads=nthreads)
+        t1 = time.perf_counter() - t0
+        n = max(1, int(seconds / max(t1, 1e-3)))
+        t0 = time.perf_counter()
+        oracle_direct.run(xd, w, n, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        return n, dt, n * NY * NX / dt / 1e9
+
+    n, dt, value = rate(budget_s, 0)
+    n1, dt1, value1 = rate(budget_s / 3, 1)
     pts = sample_points(NY, NX, 16, seed=1)
     ref = cone_sample(x0, w, SWEEPS, pts)
     vals = np.array([gpu_out[y, x] for (y, x) in pts], dtype=np.float64)
     err = float(np.abs(vals - ref).max() / np.abs(ref).max())
-    return {"value": n * NY * NX / dt / 1e9, "unit": "GStencil/s", "cores": oracle_direct.threads(),
+    return {"value": value, "unit": "GStencil/s", "cores": oracle_direct.threads(),
             "kind": "oracle",
             "sample": f"{n} full-grid FP64 sweeps of the 10240^2 Box-2D9P grid ({dt:.1f} s); "
-                      f"error check on 16 sampled outputs of the 100-sweep run via dependency cones"}, err
+                      f"error check on 16 sampled outputs of the 100-sweep run via dependency cones",
+            "single_thread": {"value": value1, "unit": "GStencil/s", "cores": 1,
+                              "sample": f"{n1} full-grid FP64 sweeps on one thread ({dt1:.1f} s)"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}, err
 
 
 def timed_run(torch, plan, x_dev, steps, stream, reps=1):
@@ -281,13 +302,14 @@ def check_workloads(checks):
 SERVE_DTYPES = {"f32": "f32_split_f16", "split_bf16": "f32_split_bf16"}
 
 
-def serving_leg(native, torch, n_jobs: int, load: float):
+def serving_leg(native, torch, n_jobs: int, loads):
     """Serving mix: jobs of several stencils, sizes, step counts and dtypes
     through one server (2-D radius-1 and 1-D jobs with three sweeps fused
-    per launch).  Three passes over the same jobs: all submitted at
-    once (batch capacity), one job at a time through sparstencil_run, and
-    Poisson arrivals at `load` x the batch capacity (latency percentiles from
-    arrival to result)."""
+    per launch).  Passes over the same jobs: all submitted at once (batch
+    capacity), one job at a time through sparstencil_run, and Poisson
+    arrivals at each of `loads` x the batch capacity (latency percentiles
+    from arrival to result).  The server's arena is the free HBM
+    (hipMemGetInfo, through torch) less a margin."""
     import synthetic
 
     jobs = synthetic.job_stream(n_jobs, rate_per_s=1.0)
@@ -315,8 +337,15 @@ def serving_leg(native, torch, n_jobs: int, load: float):
         j["plan"] = plans[key]
         j["points"] = int(np.prod(j["grid"]))
     total_ps = sum(j["points"] * j["steps"] for j in jobs)
+    torch.cuda.synchronize()
+    free, total_hbm = torch.cuda.mem_get_info()
+    # admission by the HBM left after the inputs: the free bytes less a
+    # margin of 5% of the device (at least 8 GiB) for the runtime and torch
+    margin = max(8 << 30, total_hbm // 20)
+    arena_bytes = (free - margin) // (1 << 20) * (1 << 20)
     largest = max(p.grid_bytes for p in plans.values())
-    arena_bytes = max(16 << 30, 4 * largest)
+    if arena_bytes < 4 * largest:
+        raise RuntimeError(f"free HBM ({free} B) leaves no room for the serving arena")
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
@@ -327,26 +356,38 @@ def serving_leg(native, torch, n_jobs: int, load: float):
         return srv.clock() - t0, ids
 
     with native.Server(arena, arena_bytes, max_jobs=n_jobs, num_streams=4) as srv:
-        batch(srv)  # warm-up: first launches of every kernel variant
-        makespan, _ = batch(srv)
-        capacity = n_jobs / makespan
-        rate = load * capacity
-        arrivals = synthetic.job_stream(n_jobs, rate_per_s=rate)
-        ids = []
-        t0 = time.perf_counter()
-        for j, a in zip(jobs, arrivals):
-            wait = a["arrival"] - (time.perf_counter() - t0)
-            if wait > 0:
-                time.sleep(wait)
-            ids.append(srv.submit(j["plan"], inputs[j["grid"]], sinks[j["grid"]], j["steps"]))
-        srv.drain()
-        lat = []
+        _, ids = batch(srv)  # warm-up: first launches of every kernel variant
         for jid in ids:
-            st, info = srv.poll(jid)
-            if st != native.SS_OK:
-                raise RuntimeError(f"serving job failed: {native.status_string(st)}")
-            lat.append((info["t_done"] - info["t_submit"]) * 1e3)
-        open_span = time.perf_counter() - t0
+            srv.release(jid)
+        makespan, ids = batch(srv)
+        for jid in ids:
+            srv.release(jid)
+        capacity = n_jobs / makespan
+        open_loop = []
+        for load in loads:
+            arrivals = synthetic.job_stream(n_jobs, rate_per_s=load * capacity)
+            ids = []
+            t0 = time.perf_counter()
+            for j, a in zip(jobs, arrivals):
+                wait = a["arrival"] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(wait)
+                ids.append(srv.submit(j["plan"], inputs[j["grid"]], sinks[j["grid"]], j["steps"]))
+            srv.drain()
+            lat = []
+            for jid in ids:
+                st, info = srv.poll(jid)
+                if st != native.SS_OK:
+                    raise RuntimeError(f"serving job failed: {native.status_string(st)}")
+                lat.append((info["t_done"] - info["t_submit"]) * 1e3)
+                srv.release(jid)
+            span = time.perf_counter() - t0
+            lat = np.array(lat)
+            open_loop.append({"load": load, "gstencil_s": round(total_ps / span / 1e9, 2),
+                              "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                             "p99": round(float(np.percentile(lat, 99)), 3)}})
+            print(f"serving load {load}: p50 {open_loop[-1]['latency_ms']['p50']} ms, "
+                  f"p99 {open_loop[-1]['latency_ms']['p99']} ms", file=sys.stderr, flush=True)
 
     # one job at a time through sparstencil_run on one stream
     stream = torch.cuda.current_stream()
@@ -361,7 +402,7 @@ def serving_leg(native, torch, n_jobs: int, load: float):
     seq = time.perf_counter() - t0
     for p in plans.values():
         p.close()
-    lat = np.array(lat)
+    mid = min(open_loop, key=lambda r: abs(r["load"] - 0.7))
     return {
         "jobs": n_jobs,
         "mix": "Poisson stream over 1D 5-point 2^20, 2D 5/9/13-point 1024^2-8192^2, 3D 7/27-point "
@@ -371,11 +412,11 @@ def serving_leg(native, torch, n_jobs: int, load: float):
         "batch_gstencil_s": round(total_ps / makespan / 1e9, 2),
         "one_at_a_time_gstencil_s": round(total_ps / seq / 1e9, 2),
         "capacity_jobs_s": round(capacity, 2),
-        "load": load,
-        "open_loop_gstencil_s": round(total_ps / open_span / 1e9, 2),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
-                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "open_loop": open_loop,
+        "load": mid["load"],
+        "latency_ms": mid["latency_ms"],
         "arena_gib": round(arena_bytes / 2 ** 30, 2),
+        "arena_rule": "free HBM at server start (hipMemGetInfo) less max(8 GiB, 5% of the device)",
     }
 
 
@@ -505,7 +546,8 @@ def main():
     if not args.no_workloads:
         line["workloads"], checks = workloads_leg(native, torch, stream)
     if args.serve_jobs > 0:
-        line["serving"] = serving_leg(native, torch, args.serve_jobs, args.serve_load)
+        loads = [float(v) for v in args.serve_loads.split(",") if v]
+        line["serving"] = serving_leg(native, torch, args.serve_jobs, loads)
     if not args.no_cpu:
         cb, err = cpu_baseline(x0, w, gpu_out, args.cpu_seconds)
         line["cpu_baseline"] = cb

@@ -76,6 +76,8 @@ int oracle_direct_run(int ndim, const int64_t *dims, int radius, const double *w
         r[3 - ndim + d] = radius;
     }
 #ifdef _OPENMP
+    /* a thread count asked for holds for this call only */
+    const int prev_threads = omp_get_max_threads();
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
     (void)nthreads;
@@ -86,6 +88,9 @@ int oracle_direct_run(int ndim, const int64_t *dims, int radius, const double *w
         double *tmp = a; a = b; b = tmp;
     }
     if (a != x) memcpy(x, a, (size_t)(n[0] * n[1] * n[2]) * sizeof(double));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(prev_threads);
+#endif
     return 0;
 }
 
