@@ -31,7 +31,10 @@ BYTES_PER_POINT = 8  # FP32 state: one 4-byte read and one 4-byte write per poin
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_smfmac_box2d9p_10240.json")
 # sources of the sparse 2-D sweep kernel the traffic figure was measured on
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2506_22969_amd", "csrc", f)
-               for f in ("mma2d_impl.hpp", "mma2d_f32.hip", "kgeom.hpp", "kargs.hpp")]
+               for f in ("mma2d_conv.hpp", "mma2d_impl.hpp", "mma2d_f32_r1.hip", "mma2d_f32_r3.hip", "kgeom.hpp",
+                         "kargs.hpp")]
+SMFMAC_SPEC_TFLOPS = 5000.0   # dense-equivalent binary16 sparse peak (2x the dense 2.5 PF)
+MFMA_SPEC_TFLOPS = 2500.0
 
 
 def parse():
@@ -50,6 +53,8 @@ def parse():
                     help="jobs of the serving-mix leg (0 skips it)")
     ap.add_argument("--serve-loads", default="0.5,0.7,0.9",
                     help="Poisson arrival rates as fractions of the measured batch capacity")
+    ap.add_argument("--no-layouts", dest="layouts", action="store_false",
+                    help="skip the measured sweep over the instantiated tiles")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
     ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p", "heat1d3p", "1d5p"],
@@ -124,6 +129,71 @@ def sweep_roofline(torch, plan, x0_dev, stream, n):
     return e0.elapsed_time(e1) / n
 
 
+def measured_peaks(native, torch, stream):
+    """Peaks measured on this device: HBM bandwidth of a plain 4 GiB
+    device-to-device copy (read + write bytes), and the matrix-core probe's
+    dense-equivalent binary16 rate, sparse and dense (HIP events)."""
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    hbm = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    out = {"hbm_copy_gbs": round(hbm, 1)}
+    wgs = 256 * 8
+    buf = torch.empty(wgs * 256 * 4, dtype=torch.float32, device="cuda:0")
+    for eng in ("smfmac", "mfma"):
+        native.sparstencil_probe_mma_peak(eng, 50, wgs, buf, stream.cuda_stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        flops = native.sparstencil_probe_mma_peak(eng, 2000, wgs, buf, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[f"{eng}_tflops"] = round(flops / (e0.elapsed_time(e1) / 1e3) / 1e12, 1)
+    return out
+
+
+def issued_mma(info) -> int:
+    """Matrix products one 2-D sweep launch issues: every work item (256 x 32
+    outputs) runs 8 waves x 4 M-block units (U * MB = 4 for every tile) x K
+    chunks x passes."""
+    items = -(-NX // 256) * -(-NY // 32)
+    chunk = 64 if info["engine_name"] == "smfmac" else 32
+    return items * 32 * (info["k_pad"] // chunk) * info["passes"]
+
+
+def layout_sweep(native, torch, w, x0_dev, stream, n):
+    """Layout exploration measured (paper Section 3.3, Eqs. 6-11; Section
+    4.5): every instantiated sparse tile of the headline launch (three fused
+    sweeps, k = 7) and of the unfused sweep (k = 3), its modelled time T and
+    its measured sweep time; the model's pick is the plan's default."""
+    rows = []
+    for fuse, tiles in ((3, [(8, 8), (8, 4), (16, 2), (8, 2)]), (1, [(8, 8), (16, 4), (8, 4), (16, 2), (8, 2)])):
+        with native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac", fuse_steps=fuse) as p0:
+            pick = (p0.info["r1"], p0.info["r2"])
+            model = {(int(r[0]), int(r[1])): r for r in p0.table(native.Q_MODEL).reshape(-1, 7)}
+        for t in tiles:
+            with native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac", fuse_steps=fuse,
+                             r1=t[0], r2=t[1]) as p:
+                ms = sweep_roofline(torch, p, x0_dev, stream, n)
+                kp = p.info["k_pad"]
+            m = model.get(t)
+            rows.append({"fuse_steps": fuse, "tile": list(t), "k_pad": kp, "model_t_us": None if m is None else
+                         round(m[2] * 1e6, 2), "measured_us": round(ms * 1e3, 2), "model_pick": t == pick})
+    return rows
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -146,13 +216,15 @@ def cpu_baseline(x0: np.ndarray, w: np.ndarray, gpu_out: np.ndarray, budget_s: f
     xd = x0.astype(np.float64)
 
     def rate(seconds, nthreads):
-        t0 = time.perf_counter()
+        # runs of one sweep (the first also warms the thread pool) until
+        # `seconds` of sweeping have been timed
         oracle_direct.run(xd, w, 1, nthreads=nthreads)
-        t1 = time.perf_counter() - t0
-        n = max(1, int(seconds / max(t1, 1e-3)))
-        t0 = time.perf_counter()
-        oracle_direct.run(xd, w, n, nthreads=nthreads)
-        dt = time.perf_counter() - t0
+        n, dt = 0, 0.0
+        while dt < seconds:
+            t0 = time.perf_counter()
+            oracle_direct.run(xd, w, 1, nthreads=nthreads)
+            dt += time.perf_counter() - t0
+            n += 1
         return n, dt, n * NY * NX / dt / 1e9
 
     n, dt, value = rate(budget_s, 0)
@@ -239,6 +311,14 @@ def workloads_leg(native, torch, stream):
                lambda h: torch.from_numpy(h.view(np.int16)).to("cuda:0"), True, fuse=2, pts=pts,
                pick=lambda y, pt: y[:, pt[0], pt[1]].cpu().numpy().view(np.uint16).copy())
     del bits
+    # the headline Box-2D9P shape on a plain binary16 state (the paper's FP16
+    # setting): 10240^2, 100 sweeps, zero halo, one sweep per launch
+    w = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(NY, NX))[0]
+    x16 = synthetic.grid_f32((NY, NX), seed=0).astype(np.float16)
+    record("box2d9p_10240_f16_T100", "box", 1, w, (NY, NX), "f16", SWEEPS, ["smfmac", "mfma"], x16,
+           lambda h: torch.from_numpy(h).to("cuda:0"), False, pts=sample_points_2d(NY, NX, 8),
+           pick=lambda y, pt: float(y[pt].item()))
+    del x16
     # 3-D 512^3 FP32
     x3 = synthetic.grid_f32((512, 512, 512), seed=0)
     for name, shape, seed in [("heat3d7p_512_T20", "star", 29), ("box3d27p_512_T20", "box", 70)]:
@@ -261,6 +341,11 @@ def workloads_leg(native, torch, stream):
                lambda h: torch.from_numpy(h).to("cuda:0"), False, fuse=fuse, reps=5, pts=pts,
                pick=lambda y, pt: float(y[pt].item()))
     return out, checks
+
+
+def sample_points_2d(ny, nx, n):
+    from oracle.sampling import sample_points
+    return sample_points(ny, nx, n, seed=5)
 
 
 def check_workloads(checks):
@@ -295,6 +380,15 @@ def check_workloads(checks):
             else:
                 got = np.array(vals, dtype=np.float64)
             err = float(np.abs(got - ref).max() / np.abs(ref).max())
+            if dtype == "f16":
+                # reported as it is against FP64, and against the binary16
+                # computation the path defines
+                key16 = (name, "cones16")
+                if key16 not in cache:
+                    cache[key16] = cone_sample(x_host, w, steps, pts, periodic=periodic, binary16=True)
+                r16 = cache[key16]
+                err = {"error_vs_oracle": err,
+                       "error_vs_binary16_oracle": float(np.abs(got - r16).max() / np.abs(r16).max())}
         errs.setdefault(name, {})[eng] = err
     return errs
 
@@ -514,11 +608,20 @@ def main():
     sweep_ms = sweep_roofline(torch, plan, x0_dev, stream, args.sweep_loop)
     alg_bytes = BYTES_PER_POINT * NY * NX
     achieved = alg_bytes / (sweep_ms / 1e3) / 1e9
+    peaks = measured_peaks(native, torch, stream)
+    mma_flops = issued_mma(info) * 2.0 * 16 * 16 * 64
+    mma_tf = mma_flops / (sweep_ms / 1e3) / 1e12
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(args.fuse),
-            "kernel": "k_mma2d (sparse, binary16 split)" +
+            "kernel": "k_mma2c (sparse, binary16 split)" +
                       (f", {args.fuse} sweeps per launch, plus the edge-band launch" if args.fuse > 1 else ""),
-            "sweep_ms": round(sweep_ms, 4), "algorithmic_bytes_per_launch": alg_bytes}
+            "sweep_ms": round(sweep_ms, 4), "algorithmic_bytes_per_launch": alg_bytes,
+            "frac_of_measured_hbm": round(achieved / peaks["hbm_copy_gbs"], 4),
+            "smfmac": {"issued_dense_equiv_flops_per_launch": mma_flops, "achieved_tflops": round(mma_tf, 1),
+                       "frac_of_spec": round(mma_tf / SMFMAC_SPEC_TFLOPS, 4),
+                       "frac_of_measured": round(mma_tf / peaks["smfmac_tflops"], 4),
+                       "useful_tflops": round(2 * info["k"] ** 2 * NY * NX / (sweep_ms / 1e3) / 1e12, 2)},
+            "measured_peaks": peaks}
     if unfused.get(engines[0], {}).get("sweep_ms"):
         u_ms = unfused[engines[0]]["sweep_ms"]
         unfused[engines[0]]["roofline_frac"] = round(alg_bytes / (u_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
@@ -540,6 +643,8 @@ def main():
         "engines_unfused": unfused,
         "roofline": roof,
     }
+    if args.layouts:
+        line["layout_sweep"] = layout_sweep(native, torch, w, x0_dev, stream, max(8, args.sweep_loop // 4))
     del x0_dev
     torch.cuda.empty_cache()
     checks = []
@@ -556,7 +661,10 @@ def main():
             errs = check_workloads(checks)
             for name, per in errs.items():
                 for eng, e in per.items():
-                    line["workloads"][name][eng]["error_vs_oracle"] = e
+                    if isinstance(e, dict):
+                        line["workloads"][name][eng].update(e)
+                    else:
+                        line["workloads"][name][eng]["error_vs_oracle"] = e
     print(json.dumps(line))
 
 

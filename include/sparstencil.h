@@ -46,7 +46,10 @@ typedef enum { SS_SHAPE_BOX = 0, SS_SHAPE_STAR = 1 } ss_shape;
 typedef enum {
     SS_F64 = 0,            /* FP64 state, FP64 arithmetic                        */
     SS_F32 = 1,            /* FP32 state, FP32 arithmetic (direct engine)        */
-    SS_F16 = 2,            /* binary16 state, single-part binary16 products      */
+    SS_F16 = 2,            /* binary16 state and coefficients, one binary16
+                              product per K chunk accumulated in FP32, each
+                              sweep's result rounded to binary16 (2-D matrix
+                              engines; rows a multiple of 8 values)             */
     SS_F32_SPLIT_F16 = 3,  /* FP32 state; state and coefficients split into
                               binary16 hi + lo parts, products hi*hi + hi*lo +
                               lo*hi accumulated in FP32                         */
@@ -103,7 +106,7 @@ typedef struct ss_plan_ *ss_plan_t;
  * SS_E_UNSUPPORTED (e.g. no engine for the dtype/engine pair, a zero-halo
  * fusion outside the cases under fuse_steps, |coefficient| beyond the
  * binary16 range), SS_E_NOMEM, SS_E_DEVICE.  The matrix-core engines take
- * 2-D grids (FP32 split state or bfloat16 planes), 3-D grids (FP32 split
+ * 2-D grids (FP32 split state, bfloat16 planes or plain binary16), 3-D grids (FP32 split
  * state) and 1-D grids (FP32 split state, tiles of 16 outputs, composed
  * radius up to 8); FP64 runs on MFMA for 2-D; the direct engine takes the
  * rest.
@@ -194,6 +197,22 @@ int64_t sparstencil_launch_count(ss_plan_t plan, int64_t steps);
 size_t sparstencil_grid_bytes(ss_plan_t plan);
 
 const char *sparstencil_status_string(int32_t status);
+
+/*
+ * Matrix-core throughput probe (measurement support, not part of the
+ * method): launches `workgroups` workgroups of four waves, each wave running
+ * `iters` rounds of 8 independent binary16 products on register operands
+ * (SS_ENGINE_SMFMAC: v_smfmac_f32_16x16x64_f16; SS_ENGINE_MFMA:
+ * v_mfma_f32_16x16x32_f16), then storing its accumulators to `out`.
+ *   out    device buffer of workgroups * 256 * 4 floats (written)
+ *   flops  host; receives the dense-equivalent flops the launch issues
+ *          (2 * 16 * 16 * K per product, K = 64 sparse / 32 dense)
+ * Asynchronous on `stream`: time it with events around the call.  Errors:
+ * SS_E_INVALID (null, iters < 1, workgroups out of 1..2^20, other engine),
+ * SS_E_DEVICE (launch).
+ */
+ss_status sparstencil_probe_mma_peak(int32_t engine, int64_t iters, int32_t workgroups, float *out,
+                                     double *flops, void *stream);
 
 /*
  * Serving loop (not part of the paper's method, which runs one grid at a

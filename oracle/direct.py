@@ -2,7 +2,8 @@
 
 Test infrastructure only.  ``build()`` compiles direct.c with gcc
 (-O3 -ffp-contract=off -fopenmp) into oracle/_build/liboracle_direct.so;
-``run`` steps a float64 copy of the grid.
+``run`` steps a float64 copy of the grid; ``run_binary16`` is the same
+definition with the state and coefficients held in binary16.
 """
 from __future__ import annotations
 
@@ -70,3 +71,15 @@ def run(x, w, steps: int, periodic: bool = False, nthreads: int = 0) -> np.ndarr
     if rc != 0:
         raise ValueError("oracle_direct_run rejected its arguments")
     return a
+
+
+def run_binary16(x, w, steps: int, periodic: bool = False) -> np.ndarray:
+    """The plain binary16 computation (the paper's FP16 setting, Section 4.1):
+    coefficients and state rounded to binary16 (nearest even), each sweep's
+    sum of products formed exactly in FP64 by ``run`` and rounded to binary16.
+    Returns the binary16 grid after ``steps`` sweeps as float64."""
+    w16 = np.asarray(w, dtype=np.float64).astype(np.float16).astype(np.float64)
+    a = np.asarray(x, dtype=np.float64).astype(np.float16)
+    for _ in range(int(steps)):
+        a = run(a.astype(np.float64), w16, 1, periodic=periodic).astype(np.float16)
+    return a.astype(np.float64)

@@ -11,10 +11,12 @@ import numpy as np
 from . import direct
 
 
-def cone_sample(x0: np.ndarray, w: np.ndarray, steps: int, points, periodic: bool = False):
+def cone_sample(x0: np.ndarray, w: np.ndarray, steps: int, points, periodic: bool = False,
+                binary16: bool = False):
     """Oracle values after `steps` sweeps at the given points of a 1-, 2- or
     3-D grid (points are index tuples), each computed on its dependency cone
-    only.
+    only (FP64 sweeps, or with binary16=True the binary16 sweeps of
+    direct.run_binary16, whose roundings act point by point).
 
     A point after T sweeps depends on inputs within T*r of it along every
     axis.  Running the oracle on that window (clipped to the grid for a zero
@@ -25,18 +27,19 @@ def cone_sample(x0: np.ndarray, w: np.ndarray, steps: int, points, periodic: boo
     """
     r = (w.shape[0] - 1) // 2
     reach = steps * r
+    step = direct.run_binary16 if binary16 else direct.run
     out = []
     for pt in points:
         if periodic:
             idx = [np.arange(c - reach, c + reach + 1) % n for c, n in zip(pt, x0.shape)]
             win = x0[np.ix_(*idx)].astype(np.float64)
-            res = direct.run(win, w, steps, periodic=False)
+            res = step(win, w, steps, periodic=False)
             out.append(res[(reach,) * x0.ndim])
         else:
             lo = [max(0, c - reach) for c in pt]
             hi = [min(n, c + reach + 1) for c, n in zip(pt, x0.shape)]
             win = x0[tuple(slice(a, b) for a, b in zip(lo, hi))].astype(np.float64)
-            res = direct.run(win, w, steps, periodic=False)
+            res = step(win, w, steps, periodic=False)
             out.append(res[tuple(c - a for c, a in zip(pt, lo))])
     return np.array(out)
 

@@ -382,18 +382,44 @@ def used_columns(a: np.ndarray) -> np.ndarray:
     return np.array([bool(np.count_nonzero(a[:, c])) for c in range(a.shape[1])])
 
 
-def compact_sparse_order(a: np.ndarray, perm, kfrag: int):
+def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
+    """Kernel K order: Algorithm 1's 4-groups with the columns the stencil
+    never uses dropped and half-used groups re-paired.
+
+    With g (the patch row length, even) given, every half of a kept group is
+    also a horizontal domino (pc, pc + 1) with pc even: the columns of any
+    group with another half are taken apart into such dominoes (each once,
+    in order of first appearance) and re-paired like the halves of
+    half-used groups.  A domino pairs with the first later one that no row
+    uses in both first or both second columns."""
     used = used_columns(a)
+    aligned_only = g > 0 and g % 2 == 0
 
     def holds_used(domino):
         return any(c != ZETA and used[c] for c in domino)
 
+    def aligned(half):
+        if half == (ZETA, ZETA):
+            return True
+        c0, c1 = half
+        return c0 != ZETA and c1 == c0 + 1 and (c0 % g) % 2 == 0
+
     def rows_of(c):
         return set() if c == ZETA else set(np.flatnonzero(a[:, c]))
 
-    kept, aside = [], []
+    kept, aside, seen = [], [], set()
     for j in range(0, len(perm), 4):
         first, second = tuple(perm[j:j + 2]), tuple(perm[j + 2:j + 4])
+        if aligned_only and not (aligned(first) and aligned(second)):
+            for c in perm[j:j + 4]:
+                if c == ZETA:
+                    continue
+                d0 = c - (c % g) % 2
+                if d0 not in seen:
+                    seen.add(d0)
+                    if holds_used((d0, d0 + 1)):
+                        aside.append((d0, d0 + 1))
+            continue
         u1, u2 = holds_used(first), holds_used(second)
         if u1 and u2:
             kept.append(list(perm[j:j + 4]))

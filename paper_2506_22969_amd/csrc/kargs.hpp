@@ -90,8 +90,10 @@ struct MmaKey {
 // fills total_items and the jobs' item0 from their grid sizes.
 using MmaLaunch = hipError_t (*)(MmaArgs &, hipStream_t);
 MmaLaunch find_mma2d(const MmaKey &key);
-// Rows of a work item and the slab's elements between source rows.
-bool mma2d_geometry(const MmaKey &key, int *wgh, int *row);
+// Rows of a work item and the gather row pitch (FP32 slab: values; planes:
+// bytes; converted slab: dwords), and for a converted slab the dwords per
+// pair and pairs between row gaps (pw = 0 otherwise).
+bool mma2d_geometry(const MmaKey &key, int *wgh, int *row, int *pw, int *padg);
 // Instantiated keys with the given radius, mode, part and state (at most max).
 int mma2d_keys(int rad, int mode, int part, int state, MmaKey *out, int max);
 

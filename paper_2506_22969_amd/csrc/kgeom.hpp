@@ -15,9 +15,9 @@ constexpr int kNbCols = 2;       // units side by side across a band
 constexpr int kItemRows = 32;    // rows of a work item
 constexpr int kLdsBytes = 160 * 1024;
 
-// State layouts: FP32 values, or bfloat16 hi and lo planes ([hi | lo], each
-// a full grid of 16-bit values).
-enum State { kStateF32 = 0, kStatePlanes = 1 };
+// State layouts: FP32 values, bfloat16 hi and lo planes ([hi | lo], each a
+// full grid of 16-bit values), or plain binary16 values.
+enum State { kStateF32 = 0, kStatePlanes = 1, kStateF16 = 2 };
 
 template <int R1, int R2, int RAD, int STATE>
 struct MmaGeom {
@@ -71,6 +71,69 @@ struct MmaGeom {
     // pipeline depth: four slabs when they fit, else three
     static constexpr int NSLAB = 4 * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes ? 4 : 3;
     static_assert(NSLAB * (SLAB_BYTES + 4 * HSTRIP) <= kLdsBytes, "slabs exceed LDS");
+};
+
+// Staged-and-converted slabs of the 2-D matrix kernels on an FP32 or a
+// binary16 state.  A work item's rows land by LDS DMA in a staging slab as
+// stored: SPITCH values per row, the 256-value band between one 16-byte piece
+// of halo on either side (so RAD <= CH).  One pass then writes every
+// horizontal pair of values (columns P0 + 2j and P0 + 2j + 1 of the staging
+// row, P0 being the first column any tile reads) in the form a B register
+// takes: an FP32 pair as its packed hi word and packed lo word (PW = 2
+// dwords), a binary16 pair as one word (PW = 1).  Pair j of a converted row
+// sits at dword pos(j) = PW * (j + j / PADG): a gap of PW dwords after every
+// PADG pairs, so that the 16 tiles of a unit start in 16 different LDS banks
+// (pairs of banks for PW = 2); the row pitch ROWC is chosen for the same
+// purpose when a unit spans two tile rows.  Tile origins are whole multiples
+// of PADG pairs, so pos(origin + j) = pos(origin) + pos(j): one gather
+// offset table serves every tile.
+template <int R1, int R2, int RAD, int STATE>
+struct ConvGeom {
+    using G = MmaGeom<R1, R2, RAD, kStateF32>;         // unit arrangement
+    static constexpr int EB = STATE == kStateF16 ? 2 : 4;    // bytes per stored value
+    static constexpr int CH = 16 / EB;                       // values per 16-byte piece
+    static constexpr int SPITCH = kBandX + 2 * CH;           // staged values per row
+    static constexpr int PIECES = SPITCH / CH;               // 16-byte pieces per row
+    static constexpr int SROWS = G::SROWS;
+    static constexpr int NPIECE = SROWS * PIECES;
+    static constexpr int STAGE_BYTES = SROWS * SPITCH * EB;
+    static constexpr int P0 = CH - RAD;
+    static constexpr int NPAIR = kBandX / 2 + RAD;           // pairs per row
+    static constexpr int PW = STATE == kStateF16 ? 1 : 2;
+    static constexpr int PADG = R1 == 8 ? 4 : 8;
+    static constexpr int pos(int j) { return PW * (j + j / PADG); }
+    // first dword of each of the 16 tiles of a unit, modulo 32 banks, all
+    // different (PW = 2: all even and different)
+    static constexpr bool banks_ok(int rowc) {
+        int seen[32] = {};
+        for (int n = 0; n < 16; ++n) {
+            const int b = ((n / G::NBX) * R2 * rowc + pos((n % G::NBX) * R1 / 2)) % 32;
+            if (b % PW != 0 || seen[b]) return false;
+            seen[b] = 1;
+        }
+        return true;
+    }
+    static constexpr int pick_rowc() {
+        const int lo = (pos(NPAIR - 1) + PW + 1) / 2 * 2;
+        for (int r = lo; r < lo + 64; r += 2)
+            if (banks_ok(r)) return r;
+        return lo;
+    }
+    static constexpr int ROWC = pick_rowc();
+    static constexpr int CONV_BYTES = SROWS * ROWC * 4;
+    // a staging slab is followed by room for the transfers that round its
+    // pieces (or, FP32 rows not 16-byte aligned, values) up to whole
+    // 512-lane rounds, so that every lane of every round is active
+    static constexpr int ROUND_VEC = (NPIECE + 511) / 512 * 512 * 16;
+    static constexpr int ROUND_ELEM = STATE == kStateF32 ? (SROWS * SPITCH + 511) / 512 * 512 * 4 : 0;
+    static constexpr int STAGE_ALLOC = ROUND_VEC > ROUND_ELEM ? ROUND_VEC : ROUND_ELEM;
+    static constexpr int NSLAB = 2;                          // staging slabs
+    static constexpr int LDS_BYTES = CONV_BYTES + NSLAB * STAGE_ALLOC;
+    static_assert(STATE != kStatePlanes, "planes slabs are not converted");
+    static_assert(RAD <= CH && P0 >= 0, "halo wider than one 16-byte piece");
+    static_assert(R1 % (2 * PADG) == 0 && (G::UW / 2) % PADG == 0, "tile origins off the gap grid");
+    static_assert(banks_ok(ROWC), "no row pitch spreads the tiles over the banks");
+    static_assert(LDS_BYTES <= kLdsBytes, "slabs exceed LDS");
 };
 
 // 3-D kernel: a work item is a column of the grid (a 256-column band of

@@ -33,11 +33,13 @@ bool same_key(const MmaKey &a, const MmaKey &b) {
 
 template <class F>
 void for_each_entry(F f) {
-    int n = 0;
-    const MmaEntry *t = mma_table_f32(&n);
-    for (int i = 0; i < n; ++i) f(t[i]);
-    t = mma_table_planes(&n);
-    for (int i = 0; i < n; ++i) f(t[i]);
+    const MmaEntry *(*tables[])(int *) = {mma_table_f32_r1, mma_table_f32_r2, mma_table_f32_r3, mma_table_f16,
+                                          mma_table_planes};
+    for (auto table : tables) {
+        int n = 0;
+        const MmaEntry *t = table(&n);
+        for (int i = 0; i < n; ++i) f(t[i]);
+    }
 }
 
 }  // namespace
@@ -50,12 +52,14 @@ MmaLaunch find_mma2d(const MmaKey &k) {
     return fn;
 }
 
-bool mma2d_geometry(const MmaKey &k, int *wgh, int *row) {
+bool mma2d_geometry(const MmaKey &k, int *wgh, int *row, int *pw, int *padg) {
     bool found = false;
     for_each_entry([&](const MmaEntry &e) {
         if (!found && same_key(e.key, k)) {
             *wgh = e.wgh;
             *row = e.row;
+            *pw = e.pw;
+            *padg = e.padg;
             found = true;
         }
     });

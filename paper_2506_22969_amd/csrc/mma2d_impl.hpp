@@ -587,20 +587,27 @@ static hipError_t launch_mma2d(MmaArgs &a, hipStream_t s) {
 #define SS_MMA(R1, R2, KC, RAD, MODE, PART, STATE)                                                   \
     {{R1, R2, KC, RAD, MODE, PART, STATE},                                                           \
      &launch_mma2d<R1, R2, KC, RAD, MODE, PART, STATE>,                                              \
-     MmaGeom<R1, R2, RAD, STATE>::WGH, MmaGeom<R1, R2, RAD, STATE>::ROW}
+     MmaGeom<R1, R2, RAD, STATE>::WGH, MmaGeom<R1, R2, RAD, STATE>::ROW, 0, 0}
 
 }  // namespace ss
 
 namespace ss {
 
+// An instantiated kernel: its key, launch, rows per work item, gather row
+// pitch, and for the converted slabs (pw > 0) the dwords per pair and the
+// pairs between row gaps.
 struct MmaEntry {
     MmaKey key;
     MmaLaunch fn;
     int wgh, row;
+    int pw, padg;
 };
 
 // Tables of the instantiating translation units.
-const MmaEntry *mma_table_f32(int *n);
+const MmaEntry *mma_table_f32_r1(int *n);
+const MmaEntry *mma_table_f32_r2(int *n);
+const MmaEntry *mma_table_f32_r3(int *n);
+const MmaEntry *mma_table_f16(int *n);
 const MmaEntry *mma_table_planes(int *n);
 
 }  // namespace ss

@@ -134,9 +134,29 @@ std::vector<int> compact_groups(const Geometry &gm, const std::vector<double> &a
             if (amat[(size_t)row * kp + a] != 0.0 && amat[(size_t)row * kp + b] != 0.0) return false;
         return true;
     };
+    // with an even row length every half of a kept group is a domino
+    // (pc, pc+1), pc even; a group with another half is taken apart into such
+    // dominoes (each once, in order of first appearance)
+    const bool aligned_only = gm.g % 2 == 0;
+    auto aligned = [&](int a, int b) {
+        if (a == kZeta && b == kZeta) return true;
+        return a != kZeta && b == a + 1 && (a % gm.g) % 2 == 0;
+    };
+    std::vector<char> seen(aligned_only ? kp : 0, 0);
     std::vector<int> out;
-    std::vector<std::pair<int, int>> half;   // used dominoes of half-used groups
+    std::vector<std::pair<int, int>> half;   // used dominoes set aside for re-pairing
     for (size_t j = 0; j + 3 < perm.size(); j += 4) {
+        if (aligned_only && !(aligned(perm[j], perm[j + 1]) && aligned(perm[j + 2], perm[j + 3]))) {
+            for (size_t i = j; i < j + 4; ++i) {
+                const int c = perm[i];
+                if (c == kZeta) continue;
+                const int d0 = c - (c % gm.g) % 2;
+                if (seen[d0]) continue;
+                seen[d0] = 1;
+                if (is_used(d0) || is_used(d0 + 1)) half.emplace_back(d0, d0 + 1);
+            }
+            continue;
+        }
         const bool ua = is_used(perm[j]) || is_used(perm[j + 1]);
         const bool ub = is_used(perm[j + 2]) || is_used(perm[j + 3]);
         if (ua && ub) out.insert(out.end(), perm.begin() + j, perm.begin() + j + 4);

@@ -91,7 +91,11 @@ bool model_better(const ModelRow &a, const ModelRow &b);
 // the used dominoes of the remaining groups are re-paired first fit, in
 // order, with the first later domino whose two columns share no nonzero row
 // with theirs (else with a zero domino); kept groups first, then the new
-// ones, zero groups up to a multiple of kfrag.  Dense: the column pairs
+// ones, zero groups up to a multiple of kfrag.  With an even patch row
+// length g every kept half is also a domino (pc, pc+1) with pc even: a group
+// with another half (Algorithm 1's in-block pairs (u, u+s2) with s2 odd) is
+// taken apart into such dominoes, each once in order of first appearance,
+// which join the re-pairing.  Dense: the column pairs
 // (c, c+1), c even, of the natural order that hold a used column, zero
 // columns up to a multiple of kfrag.  With every column used (box stencils)
 // both return the plain orders.

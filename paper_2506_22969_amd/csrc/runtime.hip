@@ -53,11 +53,12 @@ bool valid_star(const std::vector<double> &w, int ndim, int r) {
 // operand layout with its index words; dense: A' columns in kperm order.
 // Gather offsets are in bytes from the tile's patch origin within one input
 // plane of the slab: FP32 rows `pitch` values apart (the 3-D kernel picks the
-// plane per K chunk), or bfloat16 planes rows of interleaved hi/lo dword
-// pairs `pitch` bytes apart.
+// plane per K chunk), bfloat16 planes rows of interleaved hi/lo dword pairs
+// `pitch` bytes apart, or (pw > 0) converted rows `pitch` dwords apart whose
+// pair j sits at dword pw * (j + j / padg).
 ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<int> &kperm, int mode, int part,
-                           int kc_count, int pitch, bool planes, std::vector<uint8_t> *blob, size_t *off_hi,
-                           size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
+                           int kc_count, int pitch, bool planes, int pw, int padg, std::vector<uint8_t> *blob,
+                           size_t *off_hi, size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
     const int MB = gm.m_prime() / 16;
     const std::vector<double> amat = morph_matrix(gm, p->w);
     const int kp = gm.k_prime();
@@ -117,7 +118,12 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
                 int32_t o = 0;
                 if (col != kZeta) {
                     const int pr = (col % plane) / gm.g, pc = col % gm.g;
-                    if (planes) {
+                    if (pw > 0) {
+                        // the register's pair starts at an even patch column
+                        if (pc % 2) return SS_E_UNSUPPORTED;
+                        const int j = pc / 2;
+                        o = 4 * (pr * pitch + pw * (j + j / padg));
+                    } else if (planes) {
                         // slab rows of interleaved hi/lo dword pairs (pitch
                         // in bytes): value column c sits at byte
                         // 8 * (c / 2) + 2 * (c % 2) of the row (hi; lo 4
@@ -199,7 +205,9 @@ ss_status upload(ss_plan_ *p, const std::vector<uint8_t> &blob) {
 }
 
 // State layout of a dtype on the MMA path.
-int mma_state(int dtype) { return dtype == SS_SPLIT_BF16 ? kStatePlanes : kStateF32; }
+int mma_state(int dtype) {
+    return dtype == SS_SPLIT_BF16 ? kStatePlanes : dtype == SS_F16 ? kStateF16 : kStateF32;
+}
 
 // The slab-pipelined kernels (matrix-core and LDS direct) address a work
 // item's rows, and a 3-D plane's rows, with 32-bit offsets: a 2-D item of
@@ -207,7 +215,7 @@ int mma_state(int dtype) { return dtype == SS_SPLIT_BF16 ? kStatePlanes : kState
 // grids run on the plain direct kernel (64-bit indexing).
 bool slab_offsets_fit(const ss_plan_ *p) {
     const int64_t nx = p->dims[2], ny = p->dims[1];
-    const int64_t bytes = p->dtype == SS_F64 ? 8 : p->dtype == SS_SPLIT_BF16 ? 2 : 4;
+    const int64_t bytes = p->dtype == SS_F64 ? 8 : (p->dtype == SS_SPLIT_BF16 || p->dtype == SS_F16) ? 2 : 4;
     const int64_t limit = (int64_t)1 << 31;
     if (p->ndim == 3) return ny * nx * bytes < limit;
     return (int64_t)kItemRows * nx * bytes < limit;
@@ -223,20 +231,22 @@ std::vector<int> kernel_order(const ss_plan_ *p, const Geometry &gm, int mode) {
 }
 
 ss_status plan_mma2d(ss_plan_ *p, int engine) {
-    const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
+    const int part = (p->dtype == SS_F32_SPLIT_F16 || p->dtype == SS_F16) ? kPartF16 : kPartBF16;
     const int state = mma_state(p->dtype);
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
+    // plain binary16: one product of the rounded coefficients and state
+    const int passes = state == kStateF16 ? 1 : 3;
     if (!slab_offsets_fit(p)) return SS_E_UNSUPPORTED;
-    // the planes kernels move rows in 8-value (16-byte) pieces
-    if (state == kStatePlanes && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
+    // the planes and binary16 kernels move rows in 8-value (16-byte) pieces
+    if ((state == kStatePlanes || state == kStateF16) && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
     ModelParams mp{};
     mp.ndim = p->ndim;
     mp.k = p->k;
     for (int d = 0; d < 3; ++d) mp.dims[d] = d < p->ndim ? p->dims[3 - p->ndim + d] : 1;
-    mp.elem_bytes = state == kStatePlanes ? 2 : 4;
+    mp.elem_bytes = state == kStateF32 ? 4 : 2;
     mp.planes_state = state == kStatePlanes ? 2 : 1;
     mp.coef_bytes = 2;
-    mp.passes = 3;
+    mp.passes = passes;
     mp.kfrag = 64;
     // tiles this build has kernels for
     MmaKey keys[32];
@@ -247,8 +257,9 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
         if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
         const Geometry gm = make_geometry(2, p->k, c.r1, c.r2);
         if (mode == kDense && gm.g % 2) continue;
-        if (mode == kSparse && !pair_aligned(gm, group_pairs(matrix_pairs(gm), 64))) continue;
-        if ((int)kernel_order(p, gm, mode).size() != (mode == kSparse ? 64 : 32) * c.kc) continue;
+        const std::vector<int> order = kernel_order(p, gm, mode);
+        if (mode == kSparse && !pair_aligned(gm, order)) continue;
+        if ((int)order.size() != (mode == kSparse ? 64 : 32) * c.kc) continue;
         cands.push_back(c);
     }
     if (cands.empty()) return SS_E_UNSUPPORTED;
@@ -273,11 +284,11 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const std::vector<int> kperm = kernel_order(p, gm, mode);
     if (mode == kSparse && !pair_aligned(gm, kperm)) return SS_E_UNSUPPORTED;
     p->kperm.assign(kperm.begin(), kperm.end());
-    int wgh, row;
-    if (!mma2d_geometry(key, &wgh, &row)) return SS_E_UNSUPPORTED;
+    int wgh, row, pw, padg;
+    if (!mma2d_geometry(key, &wgh, &row, &pw, &padg)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, kperm, mode, part, key.kc, row, state == kStatePlanes, &blob, &o_hi,
+    st = build_mma_tables(p, gm, kperm, mode, part, key.kc, row, state == kStatePlanes, pw, padg, &blob, &o_hi,
                           &o_lo, &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
     // the planes kernels of an even radius read each B register's hi and lo
@@ -290,7 +301,7 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     char *d = static_cast<char *>(p->dev);
     p->mma = find_mma2d(key);
     p->margs.periodic = p->boundary == SS_BC_PERIODIC;
-    p->margs.inv_sigma = part == kPartF16 ? 1.0f / 2048.0f : 1.0f;
+    p->margs.inv_sigma = part == kPartF16 && passes == 3 ? 1.0f / 2048.0f : 1.0f;
     p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
     p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
     p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
@@ -305,8 +316,8 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     p->info.m_prime = gm.m_prime();
     p->info.k_prime = gm.k_prime();
     p->info.k_pad = (int)p->perm.size();
-    p->info.passes = 3;
-    p->info.sigma = part == kPartF16 ? 2048.0 : 1.0;
+    p->info.passes = passes;
+    p->info.sigma = part == kPartF16 && passes == 3 ? 2048.0 : 1.0;
     return SS_OK;
 }
 
@@ -380,7 +391,7 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
     p->kperm.assign(kperm.begin(), kperm.end());
-    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, 0, 0, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
                           &o_zero);
     if (st != SS_OK) return st;
     st = upload(p, blob);
@@ -521,7 +532,8 @@ ss_status plan_mma1d(ss_plan_ *p, int engine) {
     p->kperm.assign(kperm.begin(), kperm.end());
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, kperm, mode, part, 1, 0, false, &blob, &o_hi, &o_lo, &o_idx, &o_boff, &o_zero);
+    st = build_mma_tables(p, gm, kperm, mode, part, 1, 0, false, 0, 0, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+                          &o_zero);
     if (st != SS_OK) return st;
     const MmaLaunch fn = find_mma1d(p->rad, mode, part);
     if (!fn) return SS_E_UNSUPPORTED;
@@ -678,10 +690,11 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16 || dtype == SS_SPLIT_BF16;
     int engine = o.engine;
     const bool split3 = split && dtype != SS_SPLIT_BF16;  // 3-D kernels take an FP32 state
-    if (split && ndim == 2 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
+    const bool mma2 = split || dtype == SS_F16;   // state types of the 2-D matrix kernels
+    if (mma2 && ndim == 2 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
         st = plan_mma2d(p, SS_ENGINE_SMFMAC);
         if (st != SS_OK && engine == SS_ENGINE_AUTO) st = plan_mma2d(p, SS_ENGINE_MFMA);
-    } else if (split && ndim == 2 && engine == SS_ENGINE_MFMA) {
+    } else if (mma2 && ndim == 2 && engine == SS_ENGINE_MFMA) {
         st = plan_mma2d(p, SS_ENGINE_MFMA);
     } else if (split3 && ndim == 3 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
         st = plan_mma3d(p, SS_ENGINE_SMFMAC);

@@ -29,7 +29,7 @@ EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destr
            "sparstencil_sweep", "sparstencil_sweep_batch", "sparstencil_launch_count", "sparstencil_grid_bytes",
            "sparstencil_status_string", "sparstencil_server_create", "sparstencil_submit",
            "sparstencil_poll", "sparstencil_job_release", "sparstencil_server_drain",
-           "sparstencil_server_clock", "sparstencil_server_destroy"]
+           "sparstencil_server_clock", "sparstencil_server_destroy", "sparstencil_probe_mma_peak"]
 
 
 class SparStencilError(RuntimeError):
@@ -124,6 +124,8 @@ def lib():
         L.sparstencil_server_clock.argtypes = [vp]
         L.sparstencil_server_destroy.restype = i32
         L.sparstencil_server_destroy.argtypes = [vp]
+        L.sparstencil_probe_mma_peak.restype = i32
+        L.sparstencil_probe_mma_peak.argtypes = [i32, i64, i32, vp, ctypes.POINTER(ctypes.c_double), vp]
         _lib = L
     return _lib
 
@@ -242,6 +244,15 @@ def sparstencil_server_clock(server: int) -> float:
 
 def sparstencil_server_destroy(server: int) -> None:
     _check(lib().sparstencil_server_destroy(server), "sparstencil_server_destroy")
+
+
+def sparstencil_probe_mma_peak(engine, iters: int, workgroups: int, out, stream=None) -> float:
+    """Enqueue the matrix-core throughput probe; returns the dense-equivalent
+    flops it issues (time it with events around the call)."""
+    flops = ctypes.c_double(0.0)
+    _check(lib().sparstencil_probe_mma_peak(ENGINES.get(engine, engine), int(iters), int(workgroups), _ptr(out),
+                                            ctypes.byref(flops), stream or 0), "sparstencil_probe_mma_peak")
+    return float(flops.value)
 
 
 # ----------------------------------------------------------------------------

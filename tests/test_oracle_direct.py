@@ -181,3 +181,92 @@ def test_cone_sample_1d_equals_operator_power(n, radius, steps, periodic):
     got = cone_sample(x, w, steps, pts, periodic=periodic)
     want = np.array([full[p[0]] for p in pts])
     assert np.max(np.abs(got - want)) <= 1e-13
+
+
+def test_binary16_rounding_is_exact_rne():
+    """The binary16 oracle rounds with numpy's float64 -> float16 conversion:
+    pinned against exact rational round-to-nearest-even on random values,
+    exact ties (odd and even neighbours), subnormals and values near the
+    largest finite number."""
+    from oracle import fpformat
+    rng = np.random.default_rng(3)
+    vals = list(rng.uniform(-4, 4, 2000)) + list(rng.uniform(-1e-6, 1e-6, 500))
+    # ties halfway between binary16 neighbours around 1 (spacing 2^-10)
+    vals += [1.0 + (2 * i + 1) * 2.0 ** -11 for i in range(64)]
+    vals += [-(1.0 + (2 * i + 1) * 2.0 ** -11) for i in range(64)]
+    vals += [(2 * i + 1) * 2.0 ** -25 for i in range(32)]          # subnormal ties
+    vals += [65504.0, 65519.0, -65504.0, 6.1e-5, 5.96e-8, 0.0]
+    for v in vals:
+        ref = fpformat.round_rne(float(v), fpformat.BINARY16)
+        assert ref is not None
+        assert float(np.float16(v)) == ref, v
+
+
+def _binary16_bruteforce(x, w, steps):
+    """Pure-Python binary16 sweeps on a tiny zero-halo 2-D grid: exact
+    rational sums of the rounded coefficients times the rounded state,
+    rounded once per sweep."""
+    from fractions import Fraction
+
+    from oracle import fpformat
+    k = w.shape[0]
+    r = k // 2
+    ny, nx = x.shape
+    wr = [[Fraction(fpformat.round_rne(float(w[a, b]), fpformat.BINARY16)) for b in range(k)] for a in range(k)]
+    cur = [[Fraction(fpformat.round_rne(float(x[i, j]), fpformat.BINARY16)) for j in range(nx)] for i in range(ny)]
+    for _ in range(steps):
+        nxt = []
+        for i in range(ny):
+            row = []
+            for j in range(nx):
+                s = Fraction(0)
+                for a in range(k):
+                    for b in range(k):
+                        ii, jj = i - r + a, j - r + b
+                        if 0 <= ii < ny and 0 <= jj < nx:
+                            s += wr[a][b] * cur[ii][jj]
+                row.append(Fraction(fpformat.round_rne(float(s), fpformat.BINARY16)))
+            nxt.append(row)
+        cur = nxt
+    return np.array([[float(v) for v in row] for row in cur])
+
+
+@pytest.mark.parametrize("radius,steps", [(1, 3), (2, 2)])
+def test_binary16_run_equals_bruteforce(radius, steps):
+    """run_binary16 against exact rational arithmetic on a tiny grid.  The
+    oracle forms each sum in FP64, exact for these few binary16 products up
+    to one FP64 rounding, which can decide a binary16 tie only with
+    probability ~2^-42; the seeds here hit none."""
+    rng = np.random.default_rng(11 + radius)
+    k = 2 * radius + 1
+    w = rng.uniform(-1, 1, (k, k))
+    w /= w.sum()
+    x = rng.uniform(0, 1, (6, 7))
+    got = direct.run_binary16(x, w, steps)
+    ref = _binary16_bruteforce(x, w, steps)
+    assert np.array_equal(got, ref)
+
+
+def test_binary16_constant_field():
+    """Heat-2D coefficients and 0.75 are binary16 numbers and every partial
+    sum is exact: interior points stay 0.75."""
+    w = np.array([[0, 0.125, 0], [0.125, 0.5, 0.125], [0, 0.125, 0]])
+    x = np.full((20, 24), 0.75)
+    got = direct.run_binary16(x, w, 4)
+    assert np.all(got[4:-4, 4:-4] == 0.75)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_binary16_cone_sample_equals_full_run(periodic):
+    """Dependency-cone sampling of the binary16 sweeps (rounding acts point
+    by point, so a point's cone still fixes it) against the whole grid."""
+    from oracle.sampling import cone_sample, sample_points
+    g = np.random.Generator(np.random.PCG64(8))
+    w = g.uniform(-1, 1, (3, 3))
+    w /= np.abs(w).sum()
+    x = g.random((33, 40))
+    steps = 5
+    full = direct.run_binary16(x, w, steps, periodic=periodic)
+    pts = sample_points(33, 40, 14, seed=9)
+    got = cone_sample(x, w, steps, pts, periodic=periodic, binary16=True)
+    assert np.array_equal(got, np.array([full[p] for p in pts]))

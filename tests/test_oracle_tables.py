@@ -382,21 +382,48 @@ def test_compacted_orders_are_complete_and_24_valid(radius, fuse, r1, r2):
                 return False
         return True
 
-    for order, frag in [(T.compact_sparse_order(a, perm, 64), 64), (T.compact_dense_order(a, 32), 32)]:
+    orders = [(T.compact_sparse_order(a, perm, 64), 64, registers_adjacent(perm)),
+              (T.compact_sparse_order(a, perm, 64, d.g), 64, True), (T.compact_dense_order(a, 32), 32, True)]
+    for order, frag, adjacent in orders:
         assert len(order) % frag == 0
         cols = [c for c in order if c != T.ZETA]
         assert len(cols) == len(set(cols))
         assert used <= set(cols)
-        if frag == 32 or registers_adjacent(perm):
+        if adjacent:
             assert registers_adjacent(order)
         for kk in range(0, len(order), 2):
             if order[kk] != T.ZETA or order[kk + 1] != T.ZETA:
                 assert order[kk] in used or order[kk + 1] in used
-    sparse = T.compact_sparse_order(a, perm, 64)
-    assert len(sparse) <= len(perm)
-    for j in range(0, len(sparse), 4):
-        cols = [c for c in sparse[j:j + 4] if c != T.ZETA]
-        assert np.all(np.count_nonzero(a[:, cols], axis=1) <= 2)
+    for sparse in (T.compact_sparse_order(a, perm, 64), T.compact_sparse_order(a, perm, 64, d.g)):
+        assert len(sparse) <= len(perm)
+        for j in range(0, len(sparse), 4):
+            cols = [c for c in sparse[j:j + 4] if c != T.ZETA]
+            assert np.all(np.count_nonzero(a[:, cols], axis=1) <= 2)
+
+
+@pytest.mark.parametrize("k,r1,r2", [(7, 8, 4), (7, 16, 2), (7, 8, 2), (7, 16, 4), (3, 16, 2), (3, 8, 2)])
+def test_aligned_repairing_of_box_layouts(k, r1, r2):
+    """Box stencils at tiles where Algorithm 1 leaves in-block pairs
+    (u, u + s2) with s2 odd: the aligned order takes those groups apart into
+    dominoes (pc, pc + 1), pc even, and re-pairs them.  Brute force on A':
+    every column once, at most two nonzeros per row in every 4-group, every
+    register an aligned domino, and no more K chunks than Algorithm 1's."""
+    w = synthetic.random_coeffs("box", (k - 1) // 2, 2, seed=7, grid_shape=(64, 64))[0]
+    a, s, d = T.morph(np.asarray(w, dtype=np.float64), r1, r2)
+    perm = T.group(T.plane_pairs(d)[0], 64)
+    order = T.compact_sparse_order(a, perm, 64, d.g)
+    cols = [c for c in order if c != T.ZETA]
+    assert sorted(cols) == list(range(d.k_prime))
+    assert len(order) <= len(perm)
+    for kk in range(0, len(order), 2):
+        x, y = order[kk], order[kk + 1]
+        assert (x == T.ZETA and y == T.ZETA) or (y == x + 1 and (x % d.g) % 2 == 0)
+    for j in range(0, len(order), 4):
+        c4 = [c for c in order[j:j + 4] if c != T.ZETA]
+        assert np.all(np.count_nonzero(a[:, c4], axis=1) <= 2)
+    # Algorithm 1's own order is not aligned at these tiles
+    assert any(not (order_x == T.ZETA or (perm[kk + 1] == order_x + 1 and (order_x % d.g) % 2 == 0))
+               for kk, order_x in ((kk, perm[kk]) for kk in range(0, len(perm), 2)))
 
 
 def test_compaction_counts_fused_13_point_star_at_16x2():

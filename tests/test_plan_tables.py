@@ -176,7 +176,7 @@ def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
         wk = p.table(native.Q_COEFFS).reshape(info["k"], info["k"])
     a, s, d = T.morph(wk, info["r1"], info["r2"])
     if engine == "smfmac":
-        ref = T.compact_sparse_order(a, T.group(T.plane_pairs(d)[0], 64), 64)
+        ref = T.compact_sparse_order(a, T.group(T.plane_pairs(d)[0], 64), 64, d.g)
     else:
         ref = T.compact_dense_order(a, 32)
     assert np.array_equal(got, np.array(ref, dtype=np.int32))
