@@ -187,10 +187,33 @@ def layout_sweep(native, torch, w, x0_dev, stream, n):
             with native.Plan("box", 1, w, (NY, NX), "f32_split_f16", engine="smfmac", fuse_steps=fuse,
                              r1=t[0], r2=t[1]) as p:
                 ms = sweep_roofline(torch, p, x0_dev, stream, n)
-                kp = p.info["k_pad"]
+                kp = int(p.table(native.Q_KERNEL_PERM).size)   # the kernel's own K
             m = model.get(t)
-            rows.append({"fuse_steps": fuse, "tile": list(t), "k_pad": kp, "model_t_us": None if m is None else
+            rows.append({"workload": "box radius 1 FP32 10240^2", "fuse_steps": fuse, "tile": list(t), "k_pad": kp,
+                         "model_t_us": None if m is None else
                          round(m[2] * 1e6, 2), "measured_us": round(ms * 1e3, 2), "model_pick": t == pick})
+    # the radius-3 stencils on bfloat16 planes, two fused sweeps (k = 13)
+    import synthetic
+    bits = synthetic.grid_bf16_planes((8192, 8192), seed=0)
+    xp = torch.from_numpy(bits.view(np.int16)).to("cuda:0")
+    del bits
+    for shape, seed in (("star", 45), ("box", 277)):
+        wp = synthetic.random_coeffs(shape, 3, 2, seed=seed, grid_shape=(8192, 8192))[0]
+        with native.Plan(shape, 3, wp, (8192, 8192), "split_bf16", boundary="periodic", fuse_steps=2,
+                         engine="smfmac") as p0:
+            pick = (p0.info["r1"], p0.info["r2"])
+            model = {(int(r[0]), int(r[1])): r for r in p0.table(native.Q_MODEL).reshape(-1, 7)}
+        for t in ((16, 2), (16, 1), (8, 4), (8, 2)):
+            with native.Plan(shape, 3, wp, (8192, 8192), "split_bf16", boundary="periodic", fuse_steps=2,
+                             engine="smfmac", r1=t[0], r2=t[1]) as p:
+                ms = sweep_roofline(torch, p, xp, stream, n)
+                kp = int(p.table(native.Q_KERNEL_PERM).size)   # the kernel's own K
+            m = model.get(t)
+            rows.append({"workload": f"{shape} radius 3 bf16 planes 8192^2", "fuse_steps": 2, "tile": list(t),
+                         "k_pad": kp, "model_t_us": None if m is None else round(m[2] * 1e6, 2),
+                         "measured_us": round(ms * 1e3, 2), "model_pick": t == pick})
+    del xp
+    torch.cuda.empty_cache()
     return rows
 
 
@@ -311,6 +334,16 @@ def workloads_leg(native, torch, stream):
                lambda h: torch.from_numpy(h.view(np.int16)).to("cuda:0"), True, fuse=2, pts=pts,
                pick=lambda y, pt: y[:, pt[0], pt[1]].cpu().numpy().view(np.uint16).copy())
     del bits
+    # the same two stencils on bfloat16 hi, mid and lo planes (24 significant
+    # bits, six products per K chunk)
+    bits3 = synthetic.grid_bf16_planes3((8192, 8192), seed=0)
+    for name, shape, seed in [("star2d13p_8192_planes3_S2_T50", "star", 45), ("box2d49p_8192_planes3_S2_T50", "box", 277)]:
+        w = synthetic.random_coeffs(shape, 3, 2, seed=seed, grid_shape=(8192, 8192))[0]
+        pts = [(0, 0), (4095, 17), (8191, 8191), (1234, 6543)]
+        record(name, shape, 3, w, (8192, 8192), "split3_bf16", 50, ["smfmac", "mfma"], bits3,
+               lambda h: torch.from_numpy(h.view(np.int16)).to("cuda:0"), True, fuse=2, pts=pts,
+               pick=lambda y, pt: y[:, pt[0], pt[1]].cpu().numpy().view(np.uint16).copy())
+    del bits3
     # the headline Box-2D9P shape on a plain binary16 state (the paper's FP16
     # setting): 10240^2, 100 sweeps, zero halo, one sweep per launch
     w = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(NY, NX))[0]
@@ -367,14 +400,14 @@ def check_workloads(checks):
         else:
             key = (name, "cones")
             if key not in cache:
-                if dtype == "split_bf16":
+                if dtype in ("split_bf16", "split3_bf16"):
                     f = (x_host.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-                    x0 = f[0] + f[1]
+                    x0 = f.sum(axis=0)
                 else:
                     x0 = x_host
                 cache[key] = cone_sample(x0, w, steps, pts, periodic=periodic)
             ref = cache[key]
-            if dtype == "split_bf16":
+            if dtype in ("split_bf16", "split3_bf16"):
                 got = np.array([float((v.astype(np.uint32) << 16).view(np.float32).astype(np.float64).sum())
                                 for v in vals])
             else:

@@ -16,8 +16,8 @@
  * it (zero halo) or `in` at the index taken modulo the grid size (periodic).
  *
  * Grids are dense, row-major, slowest dimension first.  Split-state grids
- * (SS_SPLIT_BF16) hold two planes back to back: [hi (N values) | lo (N)],
- * value = hi + lo.
+ * hold their planes back to back: SS_SPLIT_BF16 [hi (N values) | lo (N)],
+ * value = hi + lo; SS_SPLIT3_BF16 [hi | mid | lo], value = hi + mid + lo.
  */
 #ifndef SPARSTENCIL_H
 #define SPARSTENCIL_H
@@ -54,7 +54,13 @@ typedef enum {
                               binary16 hi + lo parts, products hi*hi + hi*lo +
                               lo*hi accumulated in FP32                         */
     SS_F32_SPLIT_BF16 = 4, /* as above with bfloat16 parts                       */
-    SS_SPLIT_BF16 = 5      /* state stored as bfloat16 hi and lo planes          */
+    SS_SPLIT_BF16 = 5,     /* state stored as bfloat16 hi and lo planes          */
+    SS_SPLIT3_BF16 = 6     /* state stored as bfloat16 hi, mid and lo planes
+                              (value = hi + mid + lo, 24 significant bits);
+                              coefficients split into three bfloat16 parts;
+                              products hi*hi, hi*mid, mid*hi, hi*lo, lo*hi and
+                              mid*mid accumulated in FP32 (2-D matrix engines;
+                              rows a multiple of 8 values)                     */
 } ss_dtype;
 
 typedef enum { SS_BC_ZERO = 0, SS_BC_PERIODIC = 1 } ss_boundary;
@@ -126,6 +132,8 @@ enum {
     SS_Q_META = 4,        /* uint8[m'][K_pad/4][2]: positions (i0 < i1)          */
     SS_Q_HI = 5,          /* uint16[m'][K_pad/2]: hi parts (bit patterns)        */
     SS_Q_LO = 6,          /* uint16[m'][K_pad/2]: lo parts, scaled by sigma      */
+    SS_Q_MID = 11,        /* uint16[m'][K_pad/2]: mid parts (SS_SPLIT3_BF16;
+                             empty otherwise)                                    */
     SS_Q_LUT = 7,         /* int32[K_pad][3]: (pz, pr, pc), -1s for zero cols    */
     SS_Q_MODEL = 8,       /* double[n][7]: r1, r2, T, T_compute, T_global,
                              T_shared, K_pad for every candidate layout          */

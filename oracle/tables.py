@@ -333,6 +333,23 @@ def split_hilo(vals: np.ndarray, fmt: str):
     return hi, lo
 
 
+def split_three_bf16(vals: np.ndarray):
+    """Three-part bfloat16 split of FP64 coefficients: c_hi = RNE(c), c_mid =
+    RNE(c - c_hi), c_lo = RNE(c - c_hi - c_mid), each rounded once from the
+    exact FP64 remainder.  Returns uint16 bit patterns (hi, mid, lo)."""
+    spec = fpformat.BFLOAT16
+    out = [np.zeros(vals.shape, dtype=np.uint16) for _ in range(3)]
+    for idx in np.ndindex(*vals.shape):
+        r = float(vals[idx])
+        for t in range(3):
+            v = fpformat.round_rne(r, spec)
+            if v is None:
+                raise OverflowError(float(vals[idx]))
+            out[t][idx] = fpformat.bf16_bits(v)
+            r -= v
+    return tuple(out)
+
+
 def round_plain(vals: np.ndarray, fmt: str) -> np.ndarray:
     """Single-part rounding (plain FP16/BF16 paths): uint16 bit patterns."""
     spec = fpformat.BINARY16 if fmt == "f16" else fpformat.BFLOAT16
@@ -382,16 +399,12 @@ def used_columns(a: np.ndarray) -> np.ndarray:
     return np.array([bool(np.count_nonzero(a[:, c])) for c in range(a.shape[1])])
 
 
-def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
-    """Kernel K order: Algorithm 1's 4-groups with the columns the stencil
-    never uses dropped and half-used groups re-paired.
-
-    With g (the patch row length, even) given, every half of a kept group is
-    also a horizontal domino (pc, pc + 1) with pc even: the columns of any
-    group with another half are taken apart into such dominoes (each once,
-    in order of first appearance) and re-paired like the halves of
-    half-used groups.  A domino pairs with the first later one that no row
-    uses in both first or both second columns."""
+def _kept_and_aside(a: np.ndarray, perm, g: int):
+    """Algorithm 1's 4-groups both of whose halves hold a used column (and,
+    with g even, are aligned dominoes), kept in order; and the used dominoes
+    set aside for re-pairing: the used halves of half-used groups, and the
+    aligned dominoes (pc, pc + 1), pc even, of the columns of groups with a
+    half that is not one (each once, in order of first appearance)."""
     used = used_columns(a)
     aligned_only = g > 0 and g % 2 == 0
 
@@ -403,9 +416,6 @@ def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
             return True
         c0, c1 = half
         return c0 != ZETA and c1 == c0 + 1 and (c0 % g) % 2 == 0
-
-    def rows_of(c):
-        return set() if c == ZETA else set(np.flatnonzero(a[:, c]))
 
     kept, aside, seen = [], [], set()
     for j in range(0, len(perm), 4):
@@ -427,6 +437,28 @@ def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
             aside.append(first)
         elif u2:
             aside.append(second)
+    return kept, aside
+
+
+def dominoes_compatible(a: np.ndarray, d0, d1) -> bool:
+    """Two dominoes may share a 4-group [d0.0, d0.1, d1.0, d1.1]: their
+    first columns, and their second columns, are conflict-free pairs
+    (Definition 1 on the nonzeros of A')."""
+    def rows_of(c):
+        return set() if c == ZETA else set(np.flatnonzero(a[:, c]))
+    return not (rows_of(d0[0]) & rows_of(d1[0])) and not (rows_of(d0[1]) & rows_of(d1[1]))
+
+
+def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
+    """Kernel K order: Algorithm 1's 4-groups with the columns the stencil
+    never uses dropped and half-used groups re-paired first fit (each
+    set-aside domino with the first later compatible one).
+
+    With g (the patch row length, even) given, every half of a kept group is
+    also a horizontal domino (pc, pc + 1) with pc even: the columns of any
+    group with another half are taken apart into such dominoes, which join
+    the re-pairing (_kept_and_aside)."""
+    kept, aside = _kept_and_aside(a, perm, g)
     paired = [False] * len(aside)
     new = []
     for i, dom in enumerate(aside):
@@ -435,11 +467,8 @@ def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
         paired[i] = True
         partner = (ZETA, ZETA)
         for j in range(i + 1, len(aside)):
-            if paired[j]:
-                continue
-            other = aside[j]
-            if not (rows_of(dom[0]) & rows_of(other[0])) and not (rows_of(dom[1]) & rows_of(other[1])):
-                partner = other
+            if not paired[j] and dominoes_compatible(a, dom, aside[j]):
+                partner = aside[j]
                 paired[j] = True
                 break
         new.append([dom[0], dom[1], partner[0], partner[1]])
@@ -447,6 +476,23 @@ def compact_sparse_order(a: np.ndarray, perm, kfrag: int, g: int = 0):
     while len(out) % kfrag:
         out.append(ZETA)
     return out
+
+
+def max_repairing_groups(a: np.ndarray, perm, g: int):
+    """(kept groups, least number of groups the set-aside dominoes fit in):
+    the re-pairing as a maximum matching of the compatibility graph of the
+    dominoes (networkx's general-graph matching, independent of the
+    planner's)."""
+    import networkx as nx
+    kept, aside = _kept_and_aside(a, perm, g)
+    graph = nx.Graph()
+    graph.add_nodes_from(range(len(aside)))
+    for i in range(len(aside)):
+        for j in range(i + 1, len(aside)):
+            if dominoes_compatible(a, aside[i], aside[j]):
+                graph.add_edge(i, j)
+    matching = nx.max_weight_matching(graph, maxcardinality=True)
+    return kept, len(aside) - len(matching)
 
 
 def compact_dense_order(a: np.ndarray, kfrag: int):
@@ -518,8 +564,9 @@ def model_time(k: int, ndim: int, r1: int, r2: int, grid, elem_bytes: int,
 
 
 def passes_planes(passes: int) -> int:
-    """hi and lo planes are both moved through LDS in split mode."""
-    return 2 if passes > 1 else 1
+    """Parts of the operands moved through LDS: hi and lo in split mode
+    (three products), hi, mid and lo with three parts (six products)."""
+    return 3 if passes >= 6 else 2 if passes > 1 else 1
 
 
 def explore(k: int, ndim: int, grid, candidates, elem_bytes: int, coef_bytes: int,

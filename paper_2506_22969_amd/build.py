@@ -17,7 +17,8 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-ffp-contract=fast", "-Wall", "-Wno-unused-variable", "-Wno-unused-result"]
-SOURCES = ["mma2d_f32_r3.hip", "mma2d_f32_r1.hip", "mma2d_f32_r2.hip", "mma2d_f16.hip", "mma2d_planes.hip", "mma3d.hip",
+SOURCES = ["mma2d_f32_r3.hip", "mma2d_f32_r1.hip", "mma2d_f32_r2.hip", "mma2d_f16.hip", "mma2d_planes.hip",
+           "mma2d_planes3.hip", "mma3d.hip",
            "mma2d_f64.hip", "mma1d.hip", "direct2d.hip", "mma2d.hip", "direct.hip", "runtime.hip", "server.hip", "probe.hip"]
 
 

@@ -28,19 +28,25 @@ struct MmaArgs {
     int njobs;
     int total_items;         // work items over all jobs
     int nxcd;                // XCDs the launch's workgroups are dealt over
+    int item_wgs;            // workgroups that sweep work items (2-D matrix
+                             // kernels; the launch's other workgroups compute
+                             // the band of a fused zero-halo sweep)
     MmaJob job[kMaxJobs];
     int periodic;
     float inv_sigma;
     const uint4 *a_hi;       // [MB][KC][64] A fragments (8 x 16-bit each)
     const uint4 *a_lo;
+    const uint4 *a_mid;      // three-part states: the coefficients' mid parts
     const uint32_t *a_idx;   // [MB][KC][64] sparse index words (sparse mode)
     const int32_t *boff;     // [KC][4][VPK] gather offsets in bytes
     const void *zeros;       // 1 KiB of zeros (loads outside a zero-halo grid)
     const float *w;          // (2r+1)^2 coefficients (direct LDS kernel only)
-    // 1-D fused zero-halo sweeps: the unfused coefficients (FP64), radius and
-    // S; the launch then also recomputes the r(S-1) points at either end
-    // (nullptr: no end band)
+    // fused zero-halo sweeps: the unfused coefficients (FP64 for the 1-D
+    // kernels, FP32 for the 2-D ones), radius and S; the launch then also
+    // recomputes the points within r(S-1) of the edges (edge_steps < 2: no
+    // band)
     const double *edge_w;
+    const float *edge_w32;
     int edge_rad, edge_steps;
 };
 

@@ -16,8 +16,9 @@ constexpr int kItemRows = 32;    // rows of a work item
 constexpr int kLdsBytes = 160 * 1024;
 
 // State layouts: FP32 values, bfloat16 hi and lo planes ([hi | lo], each a
-// full grid of 16-bit values), or plain binary16 values.
-enum State { kStateF32 = 0, kStatePlanes = 1, kStateF16 = 2 };
+// full grid of 16-bit values), plain binary16 values, or bfloat16 hi, mid
+// and lo planes ([hi | mid | lo]).
+enum State { kStateF32 = 0, kStatePlanes = 1, kStateF16 = 2, kStatePlanes3 = 3 };
 
 template <int R1, int R2, int RAD, int STATE>
 struct MmaGeom {
@@ -76,11 +77,13 @@ struct MmaGeom {
 // Staged-and-converted slabs of the 2-D matrix kernels on an FP32 or a
 // binary16 state.  A work item's rows land by LDS DMA in a staging slab as
 // stored: SPITCH values per row, the 256-value band between one 16-byte piece
-// of halo on either side (so RAD <= CH).  One pass then writes every
-// horizontal pair of values (columns P0 + 2j and P0 + 2j + 1 of the staging
-// row, P0 being the first column any tile reads) in the form a B register
-// takes: an FP32 pair as its packed hi word and packed lo word (PW = 2
-// dwords), a binary16 pair as one word (PW = 1).  Pair j of a converted row
+// of halo on either side (so RAD <= CH), for a bfloat16 hi/lo planes state
+// the hi row and then the lo row.  One pass then writes every horizontal
+// pair of values (columns P0 + 2j and P0 + 2j + 1 of the staging row, P0
+// being the first column any tile reads) in the form a B register takes: an
+// FP32 pair as its packed hi word and packed lo word, a planes pair as its
+// hi-plane word and lo-plane word (PW = 2 dwords), a binary16 pair as one
+// word (PW = 1).  Pair j of a converted row
 // sits at dword pos(j) = PW * (j + j / PADG): a gap of PW dwords after every
 // PADG pairs, so that the 16 tiles of a unit start in 16 different LDS banks
 // (pairs of banks for PW = 2); the row pitch ROWC is chosen for the same
@@ -90,31 +93,35 @@ struct MmaGeom {
 template <int R1, int R2, int RAD, int STATE>
 struct ConvGeom {
     using G = MmaGeom<R1, R2, RAD, kStateF32>;         // unit arrangement
-    static constexpr int EB = STATE == kStateF16 ? 2 : 4;    // bytes per stored value
+    static constexpr int EB = STATE == kStateF32 ? 4 : 2;    // bytes per stored value
+    static constexpr int NPL = STATE == kStatePlanes3 ? 3 : STATE == kStatePlanes ? 2 : 1;   // stored planes
     static constexpr int CH = 16 / EB;                       // values per 16-byte piece
-    static constexpr int SPITCH = kBandX + 2 * CH;           // staged values per row
-    static constexpr int PIECES = SPITCH / CH;               // 16-byte pieces per row
+    static constexpr int SPITCH = kBandX + 2 * CH;           // staged values per row and plane
+    static constexpr int PIECES = SPITCH / CH;               // 16-byte pieces per row and plane
     static constexpr int SROWS = G::SROWS;
-    static constexpr int NPIECE = SROWS * PIECES;
-    static constexpr int STAGE_BYTES = SROWS * SPITCH * EB;
+    // a staging row holds the row of every plane, one after the other
+    static constexpr int NPIECE = SROWS * NPL * PIECES;
+    static constexpr int STAGE_BYTES = SROWS * NPL * SPITCH * EB;
     static constexpr int P0 = CH - RAD;
     static constexpr int NPAIR = kBandX / 2 + RAD;           // pairs per row
-    static constexpr int PW = STATE == kStateF16 ? 1 : 2;
+    // dwords per converted pair: one word per part (hi and lo; hi, mid and lo)
+    static constexpr int PW = STATE == kStateF16 ? 1 : STATE == kStatePlanes3 ? 3 : 2;
     static constexpr int PADG = R1 == 8 ? 4 : 8;
     static constexpr int pos(int j) { return PW * (j + j / PADG); }
     // first dword of each of the 16 tiles of a unit, modulo 32 banks, all
-    // different (PW = 2: all even and different)
+    // different (PW = 2: all even and different; PW = 3 cannot avoid every
+    // conflict of its 48 dwords, its first dwords differ)
     static constexpr bool banks_ok(int rowc) {
         int seen[32] = {};
         for (int n = 0; n < 16; ++n) {
             const int b = ((n / G::NBX) * R2 * rowc + pos((n % G::NBX) * R1 / 2)) % 32;
-            if (b % PW != 0 || seen[b]) return false;
+            if ((PW == 2 && b % 2 != 0) || seen[b]) return false;
             seen[b] = 1;
         }
         return true;
     }
     static constexpr int pick_rowc() {
-        const int lo = (pos(NPAIR - 1) + PW + 1) / 2 * 2;
+        const int lo = (pos(NPAIR - 1) + PW + 1) / 2 * 2;      // even: 8-byte aligned pairs
         for (int r = lo; r < lo + 64; r += 2)
             if (banks_ok(r)) return r;
         return lo;
@@ -127,9 +134,10 @@ struct ConvGeom {
     static constexpr int ROUND_VEC = (NPIECE + 511) / 512 * 512 * 16;
     static constexpr int ROUND_ELEM = STATE == kStateF32 ? (SROWS * SPITCH + 511) / 512 * 512 * 4 : 0;
     static constexpr int STAGE_ALLOC = ROUND_VEC > ROUND_ELEM ? ROUND_VEC : ROUND_ELEM;
-    static constexpr int NSLAB = 2;                          // staging slabs
+    // staging slabs: two, or one when two do not fit beside the converted
+    // slab (three planes of a wide stencil)
+    static constexpr int NSLAB = CONV_BYTES + 2 * STAGE_ALLOC <= kLdsBytes ? 2 : 1;
     static constexpr int LDS_BYTES = CONV_BYTES + NSLAB * STAGE_ALLOC;
-    static_assert(STATE != kStatePlanes, "planes slabs are not converted");
     static_assert(RAD <= CH && P0 >= 0, "halo wider than one 16-byte piece");
     static_assert(R1 % (2 * PADG) == 0 && (G::UW / 2) % PADG == 0, "tile origins off the gap grid");
     static_assert(banks_ok(ROWC), "no row pitch spreads the tiles over the banks");

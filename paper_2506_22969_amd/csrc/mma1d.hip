@@ -36,14 +36,14 @@ __device__ inline int skewed(int i) { return i + (i >> 4); }
 // Exact values of the points within r(S-1) of either end of every grid after
 // S zero-halo sweeps, by threads 0..63 of one workgroup, one point at a time
 // per thread: the window of inputs the point depends on is swept S times in
-// FP64 (in LDS, shrinking by r on each side per sweep) with the points
-// outside the grid held at zero.
+// FP32 (in LDS, shrinking by r on each side per sweep, FMAs in a fixed
+// order) with the points outside the grid held at zero.
 constexpr int kEdgeWin = 2 * k1Halo + 1;
 constexpr int kEdgeLanes = 64;
 
 __device__ inline int band_width(const MmaArgs &p) { return p.edge_rad * (p.edge_steps - 1); }
 
-__device__ inline void end_bands(const MmaArgs &p, double (*buf)[kEdgeWin][kEdgeLanes]) {
+__device__ inline void end_bands(const MmaArgs &p, float (*buf)[kEdgeWin][kEdgeLanes]) {
     const int lane = threadIdx.x;
     if (lane >= kEdgeLanes) return;
     const int b = band_width(p);
@@ -58,24 +58,24 @@ __device__ inline void end_bands(const MmaArgs &p, double (*buf)[kEdgeWin][kEdge
         float *out = static_cast<float *>(g.out);
         for (int i = lane; i < count; i += kEdgeLanes) {
             const int pt = i < lo_count ? i : n - (i - lo_count) - 1;
-            double(*cur)[kEdgeLanes] = buf[0];
-            double(*nxt)[kEdgeLanes] = buf[1];
+            float(*cur)[kEdgeLanes] = buf[0];
+            float(*nxt)[kEdgeLanes] = buf[1];
             for (int w = 0; w < L; ++w) {
                 const int gi = pt - R + w;
-                cur[w][lane] = (gi >= 0 && gi < n) ? (double)in[gi] : 0.0;
+                cur[w][lane] = (gi >= 0 && gi < n) ? in[gi] : 0.f;
             }
             for (int s = 1; s <= p.edge_steps; ++s) {
                 for (int w = s * p.edge_rad; w < L - s * p.edge_rad; ++w) {
                     const int gi = pt - R + w;
-                    double acc = 0.0;
-                    for (int o = 0; o < k; ++o) acc += p.edge_w[o] * cur[w + o - p.edge_rad][lane];
-                    nxt[w][lane] = (gi >= 0 && gi < n) ? acc : 0.0;
+                    float acc = 0.f;
+                    for (int o = 0; o < k; ++o) acc = __builtin_fmaf(p.edge_w32[o], cur[w + o - p.edge_rad][lane], acc);
+                    nxt[w][lane] = (gi >= 0 && gi < n) ? acc : 0.f;
                 }
-                double(*tmp)[kEdgeLanes] = cur;
+                float(*tmp)[kEdgeLanes] = cur;
                 cur = nxt;
                 nxt = tmp;
             }
-            out[pt] = (float)cur[R][lane];
+            out[pt] = cur[R][lane];
         }
     }
 }
@@ -122,11 +122,11 @@ __global__ __launch_bounds__(k1Threads) void k_mma1d(MmaArgs p) {
     static_assert(RAD >= 1 && RAD <= k1Halo, "radius within the staged halo");
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
     __shared__ __attribute__((aligned(16))) float lds[k1Words];
-    static_assert(sizeof(float) * k1Words >= sizeof(double) * 2 * kEdgeWin * kEdgeLanes, "end-band buffers fit");
+    static_assert(sizeof(float) * k1Words >= sizeof(float) * 2 * kEdgeWin * kEdgeLanes, "end-band buffers fit");
 
     // the workgroup after the last block recomputes the end bands
     if (p.edge_w && (int)blockIdx.x == p.total_items) {
-        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
+        end_bands(p, reinterpret_cast<float(*)[kEdgeWin][kEdgeLanes]>(lds));
         return;
     }
 
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(k1Threads) void k_lds1d(MmaArgs p) {
     constexpr int W = 16 + 2 * RAD;
     __shared__ __attribute__((aligned(16))) float lds[k1Words];
     if (p.edge_w && (int)blockIdx.x == p.total_items) {
-        end_bands(p, reinterpret_cast<double(*)[kEdgeWin][kEdgeLanes]>(lds));
+        end_bands(p, reinterpret_cast<float(*)[kEdgeWin][kEdgeLanes]>(lds));
         return;
     }
     int j = 0;

@@ -34,7 +34,7 @@ bool same_key(const MmaKey &a, const MmaKey &b) {
 template <class F>
 void for_each_entry(F f) {
     const MmaEntry *(*tables[])(int *) = {mma_table_f32_r1, mma_table_f32_r2, mma_table_f32_r3, mma_table_f16,
-                                          mma_table_planes};
+                                          mma_table_planes, mma_table_planes3};
     for (auto table : tables) {
         int n = 0;
         const MmaEntry *t = table(&n);

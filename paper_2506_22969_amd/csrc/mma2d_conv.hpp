@@ -1,24 +1,37 @@
 // 2-D stencil sweep as a structured-sparse (or dense) matrix product on
-// gfx950 matrix cores, for states stored as FP32 values (split into hi + lo
-// parts) or plain binary16 values (kernel template; instantiated by
-// mma2d_f32.hip and mma2d_f16.hip).
+// gfx950 matrix cores (kernel template; instantiated by mma2d_f32_r*.hip,
+// mma2d_f16.hip and mma2d_planes.hip), for a state stored as FP32 values
+// (split into binary16 or bfloat16 hi + lo parts), as bfloat16 hi and lo
+// planes, or as plain binary16 values.
 //
-// Same product as the planes kernel (mma2d_impl.hpp): one output tile of
-// r2 x r1 points is y = A'' * b'', A'' the permuted staircase coefficient
-// matrix and b'' the tile's halo'd patch gathered in the same K order (paper
-// Sections 3.1-3.3), sixteen tiles forming the N dimension of one MMA.  What
-// differs is how the patch reaches the B registers:
+// One output tile of r2 x r1 points is y = A'' * b'', A'' the permuted
+// staircase coefficient matrix and b'' the tile's halo'd input patch
+// gathered in the same K order (paper Sections 3.1-3.3); sixteen tiles form
+// the N dimension of one MMA.  The patch reaches the B registers in three
+// steps:
 //  * a work item's rows arrive by LDS DMA in a staging slab as stored;
-//  * one pass over the slab splits every horizontal pair of FP32 values once
-//    into its packed hi and lo words (or, for binary16, moves the pair's
-//    word) and writes them, side by side, into a converted slab whose row
-//    gaps put the 16 tiles of a unit in 16 different LDS banks (ConvGeom);
-//  * each gather is then one 8-byte (FP32 split) or 4-byte (binary16) LDS
+//  * one pass over the slab turns every horizontal pair of values into the
+//    words a B register takes -- an FP32 pair split once into its packed hi
+//    and lo words, a planes pair's hi-plane and lo-plane words, a binary16
+//    pair's word -- and writes them, side by side, into a converted slab
+//    whose row gaps put the 16 tiles of a unit in 16 different LDS banks
+//    (ConvGeom);
+//  * each gather is then one 8-byte (hi and lo) or 4-byte (binary16) LDS
 //    read from an address fixed for the whole launch.
 // With two staging slabs the DMA of the next two items overlaps the
 // conversion and the products of the current one.
 //
-// FP32 split: three products hi*hi + hi*lo + lo*hi accumulate in FP32 (the
+// Operand layouts (gfx950, measured against dense MFMA):
+//  * v_smfmac_f32_16x16x64_{f16,bf16}: lane l holds B column l%16 and the 16
+//    K values 16*(l/16) + e; the compressed A row l%16 holds 8 values whose
+//    pairs (2g', 2g'+1) belong to the 4-group of B lane group
+//    2*((l/16)%2) + g'/2, element group 2*((l/16)/2) + g'%2, with 2-bit
+//    positions in bits [2e+1:2e] of the index word.
+//  * v_mfma_f32_16x16x32_{f16,bf16}: lane l holds A row l%16 / B column l%16
+//    with K = 8*(l/16) + e.
+//  * accumulators: lane l holds column l%16, rows 4*(l/16) + i.
+//
+// Split states: three products hi*hi + hi*lo + lo*hi accumulate in FP32 (the
 // lo parts carry the scale sigma, divided out at the end).  Binary16: one
 // product of the binary16 coefficients and state, FP32 accumulation, the
 // result rounded to binary16.
@@ -38,7 +51,8 @@ struct CPipe {
     static constexpr int NELEM = VEC ? C::NPIECE : C::SROWS * C::SPITCH;   // transfers per item
     static constexpr int D = (NELEM + kThreads - 1) / kThreads;
     static_assert(D * kThreads * (VEC ? 16 : 4) <= C::STAGE_ALLOC, "rounds overrun the staging room");
-    static constexpr int STORES_PER_MB = (STATE == kStateF16 || VEC) ? 1 : 4;
+    static constexpr int STORES_PER_MB =
+        STATE == kStatePlanes3 ? 3 : STATE == kStatePlanes ? 2 : (STATE == kStateF16 || VEC) ? 1 : 4;
     static constexpr int M = G::U * G::MB * STORES_PER_MB;
     // VMEM operations issued after item s's loads when it is consumed: the
     // loads of the NSLAB-1 items issued after it and the stores of the items
@@ -70,12 +84,14 @@ __device__ inline void issue_staged(const void *zero_block, const MmaJob &g, cha
     for (int o = 0; o < P::D; ++o) {
         const int e0 = (o * kWaves + wave) * 64;      // first transfer of the instruction
         const int e = e0 + lane;
-        const int per_row = VEC ? C::PIECES : C::SPITCH;
-        const int r = e / per_row, c = e % per_row;
+        const int per_row = VEC ? C::NPL * C::PIECES : C::SPITCH;
+        const int r = e / per_row, cp = e % per_row;
+        const int pl = VEC ? cp / C::PIECES : 0, c = VEC ? cp % C::PIECES : cp;   // plane, piece
         const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
         const int gx = wrap<BC>(X0 - C::CH + (VEC ? c * C::CH : c), g.nx);
         const bool ok = e < P::NELEM && (BC != kBcZero || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx));
-        const char *src = ok ? in + ((size_t)gy * g.nx + gx) * C::EB : zeros + (VEC ? 16 : 4) * lane;
+        const size_t at = (size_t)pl * g.ny * g.nx + (size_t)gy * g.nx + gx;
+        const char *src = ok ? in + at * C::EB : zeros + (VEC ? 16 : 4) * lane;
         if constexpr (VEC)
             lds_dma16(src, base + e0 * 16);
         else
@@ -84,26 +100,40 @@ __device__ inline void issue_staged(const void *zero_block, const MmaJob &g, cha
 }
 
 // The stored pair of staging row r whose first value is pair j's: two FP32
-// values, or the word of two binary16 values (assembled from the two words
-// around it when the pair starts at an odd column).
+// values, or the word of two 16-bit values of each stored plane (assembled
+// from the two words around it when the pair starts at an odd column).
 template <int R1, int R2, int RAD, int STATE>
 struct StagedPair {
     float x0, x1;
-    unsigned w;
+    unsigned w, wl, wm;    // hi (or binary16), lo and mid words
 };
+
+// The word of the two 16-bit values at staged value index col (col even, or
+// odd and assembled from the two words around it).
+template <bool ODD>
+__device__ inline unsigned word16(const char *stage, int col) {
+    if constexpr (!ODD) {
+        return *reinterpret_cast<const unsigned *>(stage + 2 * col);
+    } else {
+        const unsigned *s = reinterpret_cast<const unsigned *>(stage + 2 * (col - 1));
+        return __builtin_amdgcn_alignbyte(s[1], s[0], 2);
+    }
+}
 
 template <int R1, int R2, int RAD, int STATE>
 __device__ inline StagedPair<R1, R2, RAD, STATE> load_pair(const char *stage, int r, int j) {
     using C = ConvGeom<R1, R2, RAD, STATE>;
-    const int col = r * C::SPITCH + C::P0 + 2 * j;
-    StagedPair<R1, R2, RAD, STATE> v{0.f, 0.f, 0u};
+    const int col = r * C::NPL * C::SPITCH + C::P0 + 2 * j;
+    StagedPair<R1, R2, RAD, STATE> v{0.f, 0.f, 0u, 0u, 0u};
     if constexpr (STATE == kStateF16) {
-        if constexpr (C::P0 % 2 == 0) {
-            v.w = *reinterpret_cast<const unsigned *>(stage + 2 * col);
-        } else {
-            const unsigned *s = reinterpret_cast<const unsigned *>(stage + 2 * (col - 1));
-            v.w = __builtin_amdgcn_alignbyte(s[1], s[0], 2);
-        }
+        v.w = word16<C::P0 % 2 != 0>(stage, col);
+    } else if constexpr (STATE == kStatePlanes) {
+        v.w = word16<C::P0 % 2 != 0>(stage, col);
+        v.wl = word16<C::P0 % 2 != 0>(stage, col + C::SPITCH);
+    } else if constexpr (STATE == kStatePlanes3) {
+        v.w = word16<C::P0 % 2 != 0>(stage, col);
+        v.wm = word16<C::P0 % 2 != 0>(stage, col + C::SPITCH);
+        v.wl = word16<C::P0 % 2 != 0>(stage, col + 2 * C::SPITCH);
     } else {
         const float *s = reinterpret_cast<const float *>(stage) + col;
         v.x0 = s[0];
@@ -120,6 +150,13 @@ __device__ inline void store_pair(char *conv, int r, int j, const StagedPair<R1,
     char *dst = conv + 4 * (r * C::ROWC + C::pos(j));
     if constexpr (STATE == kStateF16) {
         *reinterpret_cast<unsigned *>(dst) = v.w;
+    } else if constexpr (STATE == kStatePlanes) {
+        *reinterpret_cast<u2v *>(dst) = u2v{v.w, v.wl};
+    } else if constexpr (STATE == kStatePlanes3) {
+        unsigned *d = reinterpret_cast<unsigned *>(dst);
+        d[0] = v.w;
+        d[1] = v.wm;
+        d[2] = v.wl;
     } else {
         unsigned hi, lo;
         split2<PART>(v.x0, v.x1, sigma, &hi, &lo);
@@ -158,18 +195,19 @@ __device__ inline void convert_item(const char *stage, char *conv, float sigma) 
 }
 
 // Gather addresses of a lane: one 32-bit word per B register, or, where
-// that would take too many registers (32 and more), two 16-bit addresses per
-// word (a converted slab is smaller than 64 KiB), unpacked at each use.  The
-// packed word passes through an empty asm that takes a loop-varying value,
-// so that the unpacked addresses are not hoisted out of the item loop and
-// kept live (which would undo the packing).
+// that would take too many registers (32 and more), two 16-bit dword indices
+// per word (a converted slab is smaller than 256 KiB and its pairs are
+// dword-aligned), unpacked at each use.  The packed word passes through an
+// empty asm that takes a loop-varying value, so that the unpacked addresses
+// are not hoisted out of the item loop and kept live (which would undo the
+// packing).
 template <int KC, int VPK>
 struct GatherAddr {
     static constexpr bool PACK = KC * VPK >= 32;
     unsigned w[KC][PACK ? VPK / 2 : VPK];
     __device__ inline void set(int kc, int v, unsigned a) {
         if constexpr (PACK)
-            w[kc][v >> 1] = (v & 1) ? (w[kc][v >> 1] | (a << 16)) : a;
+            w[kc][v >> 1] = (v & 1) ? (w[kc][v >> 1] | ((a >> 2) << 16)) : (a >> 2);
         else
             w[kc][v] = a;
     }
@@ -177,12 +215,97 @@ struct GatherAddr {
         if constexpr (PACK) {
             unsigned x = w[kc][v >> 1];
             asm("" : "+v"(x) : "s"(salt));
-            return (v & 1) ? (x >> 16) : (x & 0xffffu);
+            return (v & 1) ? ((x >> 14) & ~3u) : ((x & 0xffffu) << 2);
         } else {
             return w[kc][v];
         }
     }
 };
+
+// Exact value at band point (y, x) after S zero-halo sweeps of the radius-1
+// stencil w (FP32, fixed order): the inputs within S of the point are read
+// once from the input grid, then each sweep is evaluated on the shrinking
+// square of points it still feeds, points outside the grid held at zero.
+template <int S>
+__device__ inline float band_value(const float *in, int ny, int nx, int y, int x, const float (&w)[3][3]) {
+    constexpr int H = S, E = 2 * H + 1;
+    float cur[E][E];
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+#pragma unroll
+        for (int c = 0; c < E; ++c) {
+            const int sy = y - H + i, sx = x - H + c;
+            const bool in_grid = sy >= 0 && sy < ny && sx >= 0 && sx < nx;
+            const int cy = min(max(sy, 0), ny - 1), cx = min(max(sx, 0), nx - 1);
+            const float v = in[(size_t)cy * nx + cx];
+            cur[i][c] = in_grid ? v : 0.f;
+        }
+#pragma unroll
+    for (int st = 1; st <= S; ++st) {
+        const int h = H - st;             // half width after sweep st
+        float nxt[E][E];
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+#pragma unroll
+            for (int c = 0; c < E; ++c) {
+                if (i < H - h || i > H + h || c < H - h || c > H + h) continue;
+                const int sy = y - H + i, sx = x - H + c;
+                float acc = 0.f;
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) acc = __builtin_fmaf(w[dy][dx], cur[i - 1 + dy][c - 1 + dx], acc);
+                nxt[i][c] = (sy >= 0 && sy < ny && sx >= 0 && sx < nx) ? acc : 0.f;
+            }
+#pragma unroll
+        for (int i = 0; i < E; ++i)
+#pragma unroll
+            for (int c = 0; c < E; ++c)
+                if (!(i < H - h || i > H + h || c < H - h || c > H + h)) cur[i][c] = nxt[i][c];
+    }
+    return cur[H][H];
+}
+
+// The band of a fused zero-halo launch (S radius-1 sweeps composed into one;
+// paper Section 4.1 fuses three): the composed stencil applied to the
+// zero-padded grid is exact only farther than S - 1 from the edges, and the
+// products leave the points within that band (widened as BandBounds says)
+// unwritten.  Band workgroup w of nb (the launch's workgroups after the
+// item workgroups) computes an equal share of the band points of all grids
+// of the launch, each as S plain sweeps in FP32 (band_value) from the input
+// grid.  The band workgroups are dispatched last: they run on the compute
+// units the item workgroups leave as they finish.
+__device__ inline void band_share(const MmaArgs &p, int wg, int nb) {
+    float w[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[i][c] = p.edge_w32[i * 3 + c];
+    long long total = 0;
+    for (int j = 0; j < p.njobs; ++j) {
+        const MmaJob &g = p.job[j];
+        total += BandShape(band_bounds(p, g), g.ny, g.nx).count(g.ny, g.nx);
+    }
+    const long long lo = total * wg / nb, hi = total * (wg + 1) / nb;
+    for (long long idx = lo + threadIdx.x; idx < hi; idx += kThreads) {
+        long long l = idx;
+        int j = 0;
+        for (; j < p.njobs - 1; ++j) {
+            const MmaJob &g = p.job[j];
+            const long long c = BandShape(band_bounds(p, g), g.ny, g.nx).count(g.ny, g.nx);
+            if (l < c) break;
+            l -= c;
+        }
+        const MmaJob &g = p.job[j];
+        const BandShape bs(band_bounds(p, g), g.ny, g.nx);
+        int y, x;
+        bs.point(l, g.nx, &y, &x);
+        const float *in = static_cast<const float *>(g.in);
+        const float v = p.edge_steps == 3 ? band_value<3>(in, g.ny, g.nx, y, x, w)
+                                          : band_value<2>(in, g.ny, g.nx, y, x, w);
+        static_cast<float *>(g.out)[(size_t)y * g.nx + x] = v;
+    }
+}
 
 // Multiply one work item out of the converted slab and write its outputs.
 // Wave w owns units (w / NCOLS) * U + u of unit column w % NCOLS; gaddr holds
@@ -190,14 +313,15 @@ struct GatherAddr {
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE, bool VEC>
 __device__ inline void compute_conv(float inv_sigma, const MmaJob &g, const char *conv,
                                     const uint4 (&ahi)[R1 * R2 / 16][KC], const uint4 (&alo)[R1 * R2 / 16][KC],
-                                    const unsigned (&aidx)[R1 * R2 / 16][KC],
+                                    const uint4 (&amid)[R1 * R2 / 16][KC], const unsigned (&aidx)[R1 * R2 / 16][KC],
                                     const GatherAddr<KC, (MODE == kSparse) ? 8 : 4> &gaddr, int X0, int Y0,
-                                    int salt) {
+                                    int salt, const BandBounds &bb) {
     using C = ConvGeom<R1, R2, RAD, STATE>;
     using G = typename C::G;
     constexpr int MB = G::MB;
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
-    constexpr bool SPLIT = STATE == kStateF32;
+    constexpr bool SPLIT = STATE != kStateF16;      // hi and lo B operands
+    constexpr bool THREE = STATE == kStatePlanes3;  // and mid operands
     // with four or more M-blocks between them, hi*lo and lo*hi of one block
     // can share an accumulator without back-to-back dependent products
     constexpr bool MERGE = MB >= 4;
@@ -217,31 +341,52 @@ __device__ inline void compute_conv(float inv_sigma, const MmaJob &g, const char
     for (int u = 0; u < G::U; ++u) {
         const int uoff = u * G::NBH * C::ROWC * 4;      // unit u's rows below unit 0's
         const int srow0 = (nb * G::U + u) * G::NBH + ty_t * R2;
-        f4 accm[MB], acc1[MB], acc2[MB];
+        // three-part products keep hi*hi, hi*mid + mid*hi, and hi*lo +
+        // lo*hi + mid*mid, each in accumulators of their own
+        f4 accm[MB], acc1[MB], acc2[MB], acc3[MB], acc4[MB], acc5[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) {
             accm[mb] = f4{0.f, 0.f, 0.f, 0.f};
             acc1[mb] = f4{0.f, 0.f, 0.f, 0.f};
             acc2[mb] = f4{0.f, 0.f, 0.f, 0.f};
+            acc3[mb] = f4{0.f, 0.f, 0.f, 0.f};
+            acc4[mb] = f4{0.f, 0.f, 0.f, 0.f};
+            acc5[mb] = f4{0.f, 0.f, 0.f, 0.f};
         }
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-            unsigned bh[VPK], bl[VPK];
+            unsigned bh[VPK], bl[VPK], bm[VPK];
 #pragma unroll
             for (int v = 0; v < VPK; ++v) {
                 const char *a = conv + gaddr.get(kc, v, salt + u) + uoff;
-                if constexpr (SPLIT) {
+                if constexpr (THREE) {
+                    const unsigned *w = reinterpret_cast<const unsigned *>(a);
+                    bh[v] = w[0];
+                    bm[v] = w[1];
+                    bl[v] = w[2];
+                } else if constexpr (SPLIT) {
                     const u2v w = *reinterpret_cast<const u2v *>(a);
                     bh[v] = w.x;
                     bl[v] = w.y;
+                    bm[v] = 0;
                 } else {
                     bh[v] = *reinterpret_cast<const unsigned *>(a);
                     bl[v] = 0;
+                    bm[v] = 0;
                 }
             }
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) accm[mb] = mma<MODE, PART>(ahi[mb][kc], bh, accm[mb], aidx[mb][kc]);
-            if constexpr (SPLIT) {
+            if constexpr (THREE) {
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb) {
+                    acc1[mb] = mma<MODE, PART>(ahi[mb][kc], bm, acc1[mb], aidx[mb][kc]);
+                    acc2[mb] = mma<MODE, PART>(amid[mb][kc], bh, acc2[mb], aidx[mb][kc]);
+                    acc3[mb] = mma<MODE, PART>(ahi[mb][kc], bl, acc3[mb], aidx[mb][kc]);
+                    acc4[mb] = mma<MODE, PART>(alo[mb][kc], bh, acc4[mb], aidx[mb][kc]);
+                    acc5[mb] = mma<MODE, PART>(amid[mb][kc], bm, acc5[mb], aidx[mb][kc]);
+                }
+            } else if constexpr (SPLIT) {
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) acc1[mb] = mma<MODE, PART>(ahi[mb][kc], bl, acc1[mb], aidx[mb][kc]);
 #pragma unroll
@@ -261,18 +406,71 @@ __device__ inline void compute_conv(float inv_sigma, const MmaJob &g, const char
             const int o = mb * 16 + 4 * q;
             const int gyr = srow0 + o / R1;
             const int gx = xbase + o % R1;
-            const bool row_ok = gyr < rows_left;
+            // the band of a fused zero-halo launch is written by band_item
+            const int gya = Y0 + gyr;
+            const bool row_ok = gyr < rows_left && gya >= bb.b && gya < g.ny - bb.b;
             float ys[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if constexpr (!SPLIT)
                     ys[i] = accm[mb][i];
+                else if constexpr (THREE)
+                    ys[i] = accm[mb][i] + ((acc1[mb][i] + acc2[mb][i]) + ((acc3[mb][i] + acc4[mb][i]) + acc5[mb][i]));
                 else if constexpr (MERGE)
                     ys[i] = accm[mb][i] + acc1[mb][i] * inv_sigma;
                 else
                     ys[i] = accm[mb][i] + (acc1[mb][i] + acc2[mb][i]) * inv_sigma;
             }
-            if constexpr (STATE == kStateF16) {
+            if constexpr (STATE == kStatePlanes3) {
+                // bfloat16 hi = RNE(y), mid = RNE(y - hi), lo = RNE(y - hi -
+                // mid) (exact differences: together they hold y); rows are
+                // a multiple of 8 values, so the four outputs are all in or
+                // all out
+                unsigned short h[3][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float r = ys[i];
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) {
+                        const __bf16 pb = (__bf16)r;
+                        h[t][i] = __builtin_bit_cast(unsigned short, pb);
+                        r -= (float)pb;
+                    }
+                }
+                unsigned short *out = static_cast<unsigned short *>(g.out);
+                const size_t plane = (size_t)g.ny * g.nx;
+                const unsigned o2 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 2u : kOob;
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const u2v hv = {(unsigned)h[t][0] | ((unsigned)h[t][1] << 16),
+                                    (unsigned)h[t][2] | ((unsigned)h[t][3] << 16)};
+                    const __amdgpu_buffer_rsrc_t rs =
+                        uniform_rsrc(out + t * plane + (size_t)Y0 * g.nx, rows_left * g.nx * 2);
+                    __builtin_amdgcn_raw_buffer_store_b64(hv, rs, o2, 0, 0);
+                }
+            } else if constexpr (STATE == kStatePlanes) {
+                // bfloat16 hi = RNE(y), lo = RNE(y - hi); rows are a
+                // multiple of 8 values, so the four outputs are all in or
+                // all out
+                unsigned short h[4], l[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const __bf16 hb = (__bf16)ys[i];
+                    const __bf16 lb = (__bf16)(ys[i] - (float)hb);
+                    h[i] = __builtin_bit_cast(unsigned short, hb);
+                    l[i] = __builtin_bit_cast(unsigned short, lb);
+                }
+                const u2v hv = {(unsigned)h[0] | ((unsigned)h[1] << 16), (unsigned)h[2] | ((unsigned)h[3] << 16)};
+                const u2v lv = {(unsigned)l[0] | ((unsigned)l[1] << 16), (unsigned)l[2] | ((unsigned)l[3] << 16)};
+                unsigned short *out = static_cast<unsigned short *>(g.out);
+                const size_t plane = (size_t)g.ny * g.nx;
+                const __amdgpu_buffer_rsrc_t rh = uniform_rsrc(out + (size_t)Y0 * g.nx, rows_left * g.nx * 2);
+                const __amdgpu_buffer_rsrc_t rl =
+                    uniform_rsrc(out + plane + (size_t)Y0 * g.nx, rows_left * g.nx * 2);
+                const unsigned o2 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 2u : kOob;
+                __builtin_amdgcn_raw_buffer_store_b64(hv, rh, o2, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(lv, rl, o2, 0, 0);
+            } else if constexpr (STATE == kStateF16) {
                 // round to binary16 (nearest even); rows are a multiple of 8
                 // values, so the four outputs are all in or all out
                 const h2v p0 = __builtin_convertvector((f2v{ys[0], ys[1]}), h2v);
@@ -288,13 +486,15 @@ __device__ inline void compute_conv(float inv_sigma, const MmaJob &g, const char
                 if constexpr (VEC) {
                     const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
                                     __float_as_uint(ys[3])};
-                    const unsigned o4 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
+                    const unsigned o4 =
+                        row_ok && gx < g.nx && gx >= bb.bl && gx < bb.br ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
                     __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o4, 0, 0);
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const unsigned o1 =
-                            row_ok && gx + i < g.nx ? (unsigned)(gyr * g.nx + gx + i) * 4u : kOob;
+                        const unsigned o1 = row_ok && gx + i < g.nx && gx + i >= bb.bl && gx + i < bb.br
+                                                ? (unsigned)(gyr * g.nx + gx + i) * 4u
+                                                : kOob;
                         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc, o1, 0, 0);
                     }
                 }
@@ -319,10 +519,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     char *conv = lds;
     auto stage = [&](int i) { return lds + C::CONV_BYTES + i * C::STAGE_ALLOC; };
 
+    if constexpr (STATE == kStateF32) {
+        if ((int)blockIdx.x >= p.item_wgs) {
+            band_share(p, (int)blockIdx.x - p.item_wgs, (int)gridDim.x - p.item_wgs);
+            return;
+        }
+    }
     const float sigma = 1.0f / p.inv_sigma;
     const float inv_sigma = p.inv_sigma;
     const int nxcd = p.nxcd;
-    const int nwg = gridDim.x;
+    const int nwg = p.item_wgs;
     const int xcd = blockIdx.x % nxcd;
     const int stride = nwg / nxcd + (xcd < nwg % nxcd ? 1 : 0);
     const int before = xcd * (nwg / nxcd) + min(xcd, nwg % nxcd);
@@ -336,7 +542,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4;
     GatherAddr<KC, VPK> gaddr;
-    static_assert(!GatherAddr<KC, VPK>::PACK || C::CONV_BYTES <= 65536, "16-bit gather addresses");
+    static_assert(!GatherAddr<KC, VPK>::PACK || C::CONV_BYTES <= 4 * 65536, "16-bit gather dword indices");
     {
         const int wave = threadIdx.x >> 6;
         const int n = lane & 15;
@@ -348,7 +554,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
 #pragma unroll
             for (int v = 0; v < VPK; ++v) gaddr.set(kc, v, (unsigned)(tile + p.boff[(kc * 4 + q) * VPK + v]));
     }
-    uint4 ahi[MB][KC], alo[MB][KC];
+    uint4 ahi[MB][KC], alo[MB][KC], amid[MB][KC];
     unsigned aidx[MB][KC];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -356,7 +562,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
         for (int kc = 0; kc < KC; ++kc) {
             const int t = (mb * KC + kc) * 64 + lane;
             ahi[mb][kc] = p.a_hi[t];
-            alo[mb][kc] = STATE == kStateF32 ? p.a_lo[t] : uint4{0u, 0u, 0u, 0u};
+            alo[mb][kc] = STATE != kStateF16 ? p.a_lo[t] : uint4{0u, 0u, 0u, 0u};
+            amid[mb][kc] = STATE == kStatePlanes3 ? p.a_mid[t] : uint4{0u, 0u, 0u, 0u};
             aidx[mb][kc] = (MODE == kSparse) ? p.a_idx[t] : 0u;
         }
     wait_vmcnt<0>();
@@ -394,8 +601,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
         const MmaJob g = p.job[j];
-        compute_conv<R1, R2, KC, RAD, MODE, PART, STATE, VEC>(inv_sigma, g, conv, ahi, alo, aidx, gaddr, X0, Y0,
-                                                              s * G::U);
+        const BandBounds bb = STATE == kStateF32 ? band_bounds(p, g) : BandBounds{0, 0, g.nx};
+        compute_conv<R1, R2, KC, RAD, MODE, PART, STATE, VEC>(inv_sigma, g, conv, ahi, alo, amid, aidx, gaddr, X0, Y0,
+                                                              s * G::U, bb);
         if (first + (s + 1) * stride >= total) break;
     }
     // the pipeline always runs NS items ahead: let those transfers land
@@ -409,15 +617,28 @@ static hipError_t launch_c_bc(const MmaArgs &a, hipStream_t s) {
     if (const hipError_t e = device_shape(&cus, &xcds); e != hipSuccess) return e;
     MmaArgs b = a;
     b.nxcd = xcds;
-    const int g = a.total_items < cus ? a.total_items : cus;
-    hipLaunchKernelGGL((k_mma2c<R1, R2, KC, RAD, MODE, PART, STATE, VEC, BC>), dim3(g), dim3(kThreads), 0, s, b);
+    b.item_wgs = a.total_items < cus ? a.total_items : cus;
+    // a fused zero-halo launch adds workgroups for the band, about two
+    // points per thread (a band has b rows at the top and at the bottom and
+    // at most 4 + b + 3 columns a row at the sides)
+    int band_wgs = 0;
+    if (STATE == kStateF32 && a.edge_steps > 1) {
+        const long long b = a.edge_rad * (a.edge_steps - 1);
+        long long pts = 0;
+        for (int j = 0; j < a.njobs; ++j) pts += 2 * b * a.job[j].nx + (b + 7) * (long long)a.job[j].ny;
+        const long long w = (pts + 2 * kThreads - 1) / (2 * kThreads);
+        band_wgs = (int)(w < 1 ? 1 : w > 4096 ? 4096 : w);
+    }
+    hipLaunchKernelGGL((k_mma2c<R1, R2, KC, RAD, MODE, PART, STATE, VEC, BC>), dim3(b.item_wgs + band_wgs),
+                       dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 
 // Number the jobs' work items, then pick the variant every job of the launch
 // can use: 16-byte pieces or 4-byte values (FP32 rows that are not a multiple
 // of 4 values), and the cheapest boundary handling valid for all of them.
-// Binary16 rows must be a multiple of 8 values (the planner checks).
+// Binary16 and planes rows must be a multiple of 8 values (the planner
+// checks).
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE>
 static hipError_t launch_mma2c(MmaArgs &a, hipStream_t s) {
     using C = ConvGeom<R1, R2, RAD, STATE>;
@@ -435,7 +656,7 @@ static hipError_t launch_mma2c(MmaArgs &a, hipStream_t s) {
     }
     a.total_items = items;
     if (items == 0) return hipSuccess;
-    if constexpr (STATE == kStateF16) {
+    if constexpr (STATE != kStateF32) {
         if (!vec) return hipErrorInvalidValue;
         if (!a.periodic) return launch_c_bc<R1, R2, KC, RAD, MODE, PART, STATE, true, kBcZero>(a, s);
         if (wrap1) return launch_c_bc<R1, R2, KC, RAD, MODE, PART, STATE, true, kBcWrap1>(a, s);

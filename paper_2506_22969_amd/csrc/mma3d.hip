@@ -20,7 +20,7 @@
 
 namespace ss {
 
-template <int R1, int R2, int RAD, bool VEC>
+template <int R1, int R2, int RAD, bool VEC, bool BAND = false>
 struct Pipe3 {
     using G = Mma3Geom<R1, R2, RAD>;
     static constexpr int DRW = (G::SROWS + kWaves - 1) / kWaves;   // rows each wave loads per plane
@@ -28,7 +28,9 @@ struct Pipe3 {
     // bytes, or 4 x 64 lanes x 4 bytes and 8 lanes x 4 bytes
     static constexpr int DMA_PER_ROW = VEC ? 2 : 5;
     static constexpr int D = DRW * DMA_PER_ROW;                    // VMEM loads per wave per plane
-    static constexpr int M = G::MB * (VEC ? 1 : 4);                // VMEM stores per wave per output plane
+    // VMEM stores per wave per output plane: one 16-byte store per M block,
+    // or four 4-byte ones (rows not 16-byte aligned, or a band to leave out)
+    static constexpr int M = G::MB * (VEC && !BAND ? 1 : 4);
     static constexpr int A = 2 * RAD;                              // steps before the first store
     // Step l waits for plane l + 1 (its B operands are gathered while the
     // matrix cores multiply plane l).  VMEM operations a wave has issued

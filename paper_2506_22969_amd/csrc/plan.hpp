@@ -18,7 +18,7 @@ struct ss_plan_ {
     std::vector<int32_t> perm;
     std::vector<double> values;
     std::vector<uint8_t> meta;
-    std::vector<uint16_t> hi, lo;
+    std::vector<uint16_t> hi, lo, mid;   // mid: three-part states only
     std::vector<int32_t> lut;
     std::vector<double> model;        // rows of 7
     std::vector<int32_t> kernel_lut;
@@ -36,7 +36,8 @@ struct ss_plan_ {
     // an edge is recomputed exactly from the unfused coefficients
     std::vector<double> w1;           // unfused coefficients
     int edge_rad = 0;
-    double *edge_w = nullptr;         // device copy of w1
+    double *edge_w = nullptr;         // device copy of w1 in FP64, then in FP32
+    float *edge_w32 = nullptr;        // the FP32 copy (inside edge_w's allocation)
 };
 
 namespace ss {
@@ -45,6 +46,7 @@ namespace ss {
 hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
                        const int64_t (*dims)[3], hipStream_t s);
 hipError_t sweep_one(const ss_plan_ *p, const void *in, void *out, hipStream_t s);
+bool band_in_launch(const ss_plan_ *p);
 size_t plan_state_bytes(const ss_plan_ *p);
 // True when a and b can share one launch: equal device tables and the same
 // kernel (a plan of the direct engine picks its kernel from its grid size).

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <numeric>
+#include <queue>
 
 namespace ss {
 
@@ -122,6 +124,87 @@ static std::vector<char> used_columns(const Geometry &gm, const std::vector<doub
     return used;
 }
 
+// Maximum-cardinality matching in a general graph (Edmonds' blossom
+// algorithm, the general matcher the paper's Section 3.2 names for
+// structures that are not staircases): grow an alternating tree from each
+// free vertex by breadth-first search; an edge between two outer vertices of
+// the tree closes an odd cycle (a blossom), whose vertices are then treated
+// as its base; an edge to a free vertex outside the tree completes an
+// augmenting path, which is flipped.  mate[v] = v's partner or -1.
+static std::vector<int> max_matching(int n, const std::vector<std::vector<int>> &adj) {
+    std::vector<int> mate(n, -1), parent(n), base(n), label(n);
+    std::vector<char> in_blossom(n), on_path(n);
+    auto lca = [&](int a, int b) {
+        std::fill(on_path.begin(), on_path.end(), 0);
+        for (;;) {
+            a = base[a];
+            on_path[a] = 1;
+            if (mate[a] < 0) break;
+            a = parent[mate[a]];
+        }
+        for (;;) {
+            b = base[b];
+            if (on_path[b]) return b;
+            b = parent[mate[b]];
+        }
+    };
+    auto mark_path = [&](int v, int b, int child) {
+        while (base[v] != b) {
+            in_blossom[base[v]] = in_blossom[base[mate[v]]] = 1;
+            parent[v] = child;
+            child = mate[v];
+            v = parent[mate[v]];
+        }
+    };
+    auto find_path = [&](int root) -> int {
+        std::fill(label.begin(), label.end(), 0);        // 0 unreached, 1 outer
+        std::fill(parent.begin(), parent.end(), -1);
+        std::iota(base.begin(), base.end(), 0);
+        std::queue<int> q;
+        label[root] = 1;
+        q.push(root);
+        while (!q.empty()) {
+            const int v = q.front();
+            q.pop();
+            for (int u : adj[v]) {
+                if (base[v] == base[u] || mate[v] == u) continue;
+                if (u == root || (mate[u] >= 0 && parent[mate[u]] >= 0)) {
+                    // u is an outer vertex: a blossom closes
+                    const int b = lca(v, u);
+                    std::fill(in_blossom.begin(), in_blossom.end(), 0);
+                    mark_path(v, b, u);
+                    mark_path(u, b, v);
+                    for (int i = 0; i < n; ++i)
+                        if (in_blossom[base[i]]) {
+                            base[i] = b;
+                            if (!label[i]) {
+                                label[i] = 1;
+                                q.push(i);
+                            }
+                        }
+                } else if (parent[u] < 0) {
+                    parent[u] = v;
+                    if (mate[u] < 0) return u;               // augmenting path found
+                    label[mate[u]] = 1;
+                    q.push(mate[u]);
+                }
+            }
+        }
+        return -1;
+    };
+    for (int v = 0; v < n; ++v) {
+        if (mate[v] >= 0) continue;
+        const int u = find_path(v);
+        for (int x = u; x >= 0;) {          // flip the path
+            const int pv = parent[x], ppv = mate[pv];
+            mate[x] = pv;
+            mate[pv] = x;
+            x = ppv;
+        }
+    }
+    return mate;
+}
+
 std::vector<int> compact_groups(const Geometry &gm, const std::vector<double> &amat, const std::vector<int> &perm,
                                 int kfrag) {
     const int mp = gm.m_prime(), kp = gm.k_prime();
@@ -163,24 +246,26 @@ std::vector<int> compact_groups(const Geometry &gm, const std::vector<double> &a
         else if (ua) half.emplace_back(perm[j], perm[j + 1]);
         else if (ub) half.emplace_back(perm[j + 2], perm[j + 3]);
     }
-    std::vector<char> taken(half.size(), 0);
-    for (size_t i = 0; i < half.size(); ++i) {
-        if (taken[i]) continue;
-        taken[i] = 1;
-        int mate = -1;
-        for (size_t j = i + 1; j < half.size() && mate < 0; ++j)
-            if (!taken[j] && apart(half[i].first, half[j].first) && apart(half[i].second, half[j].second))
-                mate = (int)j;
+    // re-pair the set-aside dominoes by a maximum matching of the graph
+    // whose edges join two dominoes that may share a 4-group: their first
+    // columns and their second columns are conflict-free pairs (Definition
+    // 1), the pairing Algorithm 1's own groups have.  Each matched couple is
+    // one group, at its smaller index; an unmatched domino gets a zero one.
+    const int nh = (int)half.size();
+    std::vector<std::vector<int>> adj(nh);
+    for (int i = 0; i < nh; ++i)
+        for (int j = i + 1; j < nh; ++j)
+            if (apart(half[i].first, half[j].first) && apart(half[i].second, half[j].second)) {
+                adj[i].push_back(j);
+                adj[j].push_back(i);
+            }
+    const std::vector<int> mate = max_matching(nh, adj);
+    for (int i = 0; i < nh; ++i) {
+        if (mate[i] >= 0 && mate[i] < i) continue;
         out.push_back(half[i].first);
         out.push_back(half[i].second);
-        if (mate >= 0) {
-            taken[mate] = 1;
-            out.push_back(half[mate].first);
-            out.push_back(half[mate].second);
-        } else {
-            out.push_back(kZeta);
-            out.push_back(kZeta);
-        }
+        out.push_back(mate[i] >= 0 ? half[mate[i]].first : kZeta);
+        out.push_back(mate[i] >= 0 ? half[mate[i]].second : kZeta);
     }
     while (out.size() % (size_t)kfrag) out.push_back(kZeta);
     return out;
@@ -359,7 +444,10 @@ ModelRow model_time(const ModelParams &mp, int r1, int r2) {
     r.t_global = (data_r + data_w) / kBwGlobal;
     // Eq. 10, reading 'm/2' as m'/2 (A' is held compressed to half width)
     const double trans = (double)gm.k_prime() * (gm.m_prime() / 2.0 + (double)tiles);
-    const double trans_rw = trans * mp.coef_bytes * (mp.passes > 1 ? 2 : 1);
+    // each part of the operands moves through LDS: one (plain), two (hi and
+    // lo: three products), three (hi, mid and lo: six products)
+    const int parts = mp.passes >= 6 ? 3 : mp.passes > 1 ? 2 : 1;
+    const double trans_rw = trans * mp.coef_bytes * parts;
     r.t_shared = (trans_rw + trans_rw) / kBwShared;
     r.t = std::max(r.t_compute, std::max(r.t_global, r.t_shared));                     // Eqs. 6, 8
     return r;

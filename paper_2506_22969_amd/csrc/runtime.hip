@@ -27,6 +27,7 @@ size_t state_bytes(int dtype) {
         case SS_F32: case SS_F32_SPLIT_F16: case SS_F32_SPLIT_BF16: return 4;
         case SS_F16: return 2;
         case SS_SPLIT_BF16: return 4;  // two 2-byte planes
+        case SS_SPLIT3_BF16: return 6; // three 2-byte planes
         default: return 0;
     }
 }
@@ -58,21 +59,32 @@ bool valid_star(const std::vector<double> &w, int ndim, int r) {
 // pair j sits at dword pw * (j + j / padg).
 ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<int> &kperm, int mode, int part,
                            int kc_count, int pitch, bool planes, int pw, int padg, std::vector<uint8_t> *blob,
-                           size_t *off_hi, size_t *off_lo, size_t *off_idx, size_t *off_boff, size_t *off_zero) {
+                           size_t *off_hi, size_t *off_lo, size_t *off_mid, size_t *off_idx, size_t *off_boff,
+                           size_t *off_zero) {
     const int MB = gm.m_prime() / 16;
     const std::vector<double> amat = morph_matrix(gm, p->w);
     const int kp = gm.k_prime();
-    auto split = [&](double c, uint16_t *h, uint16_t *l) -> bool {
+    // coefficient parts: hi + lo (binary16 lo scaled by sigma = 2^11), or for
+    // a three-part state bfloat16 hi + mid + lo, each part the rounding of
+    // what the parts before it leave
+    const bool three = p->dtype == SS_SPLIT3_BF16;
+    auto split = [&](double c, uint16_t *h, uint16_t *l, uint16_t *m) -> bool {
+        *m = 0;
         if (part == kPartF16) {
             if (!to_f16_bits(c, h)) return false;
             return to_f16_bits((c - f16_value(*h)) * 2048.0, l);
         }
         if (!to_bf16_bits(c, h)) return false;
-        return to_bf16_bits(c - bf16_value(*h), l);
+        if (!three) return to_bf16_bits(c - bf16_value(*h), l);
+        const double r = c - bf16_value(*h);
+        if (!to_bf16_bits(r, m)) return false;
+        return to_bf16_bits(r - bf16_value(*m), l);
     };
     const int VPK = mode == kSparse ? 8 : 4;
     if ((int)kperm.size() != kc_count * (mode == kSparse ? 64 : 32)) return SS_E_UNSUPPORTED;
-    std::vector<uint16_t> ahi((size_t)MB * kc_count * 64 * 8), alo(ahi.size());
+    std::vector<uint16_t> ahi((size_t)MB * kc_count * 64 * 8), alo(ahi.size()), amid(three ? ahi.size() : 0);
+    uint16_t mid_unused = 0;
+    auto mid_at = [&](size_t t) -> uint16_t * { return three ? &amid[t] : &mid_unused; };
     std::vector<uint32_t> aidx((size_t)MB * kc_count * 64, 0);
     std::vector<int32_t> boff((size_t)kc_count * 4 * VPK, 0);
     if (mode == kSparse) {
@@ -91,7 +103,7 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
                         const int j = kc * 16 + 4 * qb + m;     // 4-group of the K order
                         const size_t vi = ((size_t)r * groups + j) * 2 + s;
                         const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + ea;
-                        if (!split(cm.values[vi], &ahi[t], &alo[t])) return SS_E_UNSUPPORTED;
+                        if (!split(cm.values[vi], &ahi[t], &alo[t], mid_at(t))) return SS_E_UNSUPPORTED;
                         word |= (uint32_t)cm.meta[vi] << (2 * ea);
                     }
                     aidx[((size_t)mb * kc_count + kc) * 64 + l] = word;
@@ -105,7 +117,7 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
                         const int col = kperm[kc * 32 + 8 * (l >> 4) + e];
                         const double c = col != kZeta && col < kp ? amat[(size_t)r * kp + col] : 0.0;
                         const size_t t = (((size_t)mb * kc_count + kc) * 64 + l) * 8 + e;
-                        if (!split(c, &ahi[t], &alo[t])) return SS_E_UNSUPPORTED;
+                        if (!split(c, &ahi[t], &alo[t], mid_at(t))) return SS_E_UNSUPPORTED;
                     }
     }
     // gather offsets: K slot pair (kk, kk+1) of B register v of lane group qb
@@ -140,16 +152,19 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
                 if (o >= 65536) return SS_E_UNSUPPORTED;
                 boff[((size_t)kc * 4 + qb) * VPK + v] = o;
             }
-    // pack: a_hi | a_lo | a_idx | boff | 1 KiB of zeros, each 256-byte aligned
+    // pack: a_hi | a_lo | a_mid | a_idx | boff | 1 KiB of zeros, each
+    // 256-byte aligned (a_mid empty but for three-part states)
     auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
     *off_hi = 0;
     *off_lo = align(*off_hi + ahi.size() * 2);
-    *off_idx = align(*off_lo + alo.size() * 2);
+    *off_mid = align(*off_lo + alo.size() * 2);
+    *off_idx = align(*off_mid + amid.size() * 2);
     *off_boff = align(*off_idx + aidx.size() * 4);
     *off_zero = align(*off_boff + boff.size() * 4);
     blob->assign(*off_zero + 1024, 0);
     std::memcpy(blob->data() + *off_hi, ahi.data(), ahi.size() * 2);
     std::memcpy(blob->data() + *off_lo, alo.data(), alo.size() * 2);
+    if (three) std::memcpy(blob->data() + *off_mid, amid.data(), amid.size() * 2);
     std::memcpy(blob->data() + *off_idx, aidx.data(), aidx.size() * 4);
     std::memcpy(blob->data() + *off_boff, boff.data(), boff.size() * 4);
     p->kernel_lut = boff;
@@ -169,11 +184,17 @@ ss_status build_canonical(ss_plan_ *p, const Geometry &gm, int part, int kfrag) 
     p->meta = cm.meta;
     p->hi.resize(cm.values.size());
     p->lo.resize(cm.values.size());
+    const bool three = p->dtype == SS_SPLIT3_BF16;
+    p->mid.assign(three ? cm.values.size() : 0, 0);
     for (size_t i = 0; i < cm.values.size(); ++i) {
         const double c = cm.values[i];
         bool ok;
         if (part == kPartF16) {
             ok = to_f16_bits(c, &p->hi[i]) && to_f16_bits((c - f16_value(p->hi[i])) * 2048.0, &p->lo[i]);
+        } else if (three) {
+            ok = to_bf16_bits(c, &p->hi[i]);
+            const double r = ok ? c - bf16_value(p->hi[i]) : 0.0;
+            ok = ok && to_bf16_bits(r, &p->mid[i]) && to_bf16_bits(r - bf16_value(p->mid[i]), &p->lo[i]);
         } else {
             ok = to_bf16_bits(c, &p->hi[i]) && to_bf16_bits(c - bf16_value(p->hi[i]), &p->lo[i]);
         }
@@ -206,7 +227,10 @@ ss_status upload(ss_plan_ *p, const std::vector<uint8_t> &blob) {
 
 // State layout of a dtype on the MMA path.
 int mma_state(int dtype) {
-    return dtype == SS_SPLIT_BF16 ? kStatePlanes : dtype == SS_F16 ? kStateF16 : kStateF32;
+    return dtype == SS_SPLIT_BF16    ? kStatePlanes
+           : dtype == SS_SPLIT3_BF16 ? kStatePlanes3
+           : dtype == SS_F16         ? kStateF16
+                                     : kStateF32;
 }
 
 // The slab-pipelined kernels (matrix-core and LDS direct) address a work
@@ -215,7 +239,8 @@ int mma_state(int dtype) {
 // grids run on the plain direct kernel (64-bit indexing).
 bool slab_offsets_fit(const ss_plan_ *p) {
     const int64_t nx = p->dims[2], ny = p->dims[1];
-    const int64_t bytes = p->dtype == SS_F64 ? 8 : (p->dtype == SS_SPLIT_BF16 || p->dtype == SS_F16) ? 2 : 4;
+    const int64_t bytes =
+        p->dtype == SS_F64 ? 8 : (p->dtype == SS_SPLIT_BF16 || p->dtype == SS_SPLIT3_BF16 || p->dtype == SS_F16) ? 2 : 4;
     const int64_t limit = (int64_t)1 << 31;
     if (p->ndim == 3) return ny * nx * bytes < limit;
     return (int64_t)kItemRows * nx * bytes < limit;
@@ -234,17 +259,18 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     const int part = (p->dtype == SS_F32_SPLIT_F16 || p->dtype == SS_F16) ? kPartF16 : kPartBF16;
     const int state = mma_state(p->dtype);
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
-    // plain binary16: one product of the rounded coefficients and state
-    const int passes = state == kStateF16 ? 1 : 3;
+    // plain binary16: one product of the rounded coefficients and state;
+    // three-part states: hi*hi, hi*mid, mid*hi, hi*lo, lo*hi, mid*mid
+    const int passes = state == kStateF16 ? 1 : state == kStatePlanes3 ? 6 : 3;
     if (!slab_offsets_fit(p)) return SS_E_UNSUPPORTED;
     // the planes and binary16 kernels move rows in 8-value (16-byte) pieces
-    if ((state == kStatePlanes || state == kStateF16) && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
+    if (state != kStateF32 && p->dims[2] % 8 != 0) return SS_E_UNSUPPORTED;
     ModelParams mp{};
     mp.ndim = p->ndim;
     mp.k = p->k;
     for (int d = 0; d < 3; ++d) mp.dims[d] = d < p->ndim ? p->dims[3 - p->ndim + d] : 1;
     mp.elem_bytes = state == kStateF32 ? 4 : 2;
-    mp.planes_state = state == kStatePlanes ? 2 : 1;
+    mp.planes_state = state == kStatePlanes3 ? 3 : state == kStatePlanes ? 2 : 1;
     mp.coef_bytes = 2;
     mp.passes = passes;
     mp.kfrag = 64;
@@ -287,9 +313,9 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     int wgh, row, pw, padg;
     if (!mma2d_geometry(key, &wgh, &row, &pw, &padg)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
-    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    size_t o_hi, o_lo, o_mid, o_idx, o_boff, o_zero;
     st = build_mma_tables(p, gm, kperm, mode, part, key.kc, row, state == kStatePlanes, pw, padg, &blob, &o_hi,
-                          &o_lo, &o_idx, &o_boff, &o_zero);
+                          &o_lo, &o_mid, &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
     // the planes kernels of an even radius read each B register's hi and lo
     // parts as one dword each: every gather offset must be a whole dword
@@ -304,6 +330,7 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     p->margs.inv_sigma = part == kPartF16 && passes == 3 ? 1.0f / 2048.0f : 1.0f;
     p->margs.a_hi = reinterpret_cast<const uint4 *>(d + o_hi);
     p->margs.a_lo = reinterpret_cast<const uint4 *>(d + o_lo);
+    p->margs.a_mid = reinterpret_cast<const uint4 *>(d + o_mid);
     p->margs.a_idx = reinterpret_cast<const uint32_t *>(d + o_idx);
     p->margs.boff = reinterpret_cast<const int32_t *>(d + o_boff);
     p->margs.zeros = d + o_zero;
@@ -389,10 +416,10 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     int wgh, pitch;
     if (!mma3d_geometry(*key, &wgh, &pitch)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
-    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
+    size_t o_hi, o_lo, o_mid, o_idx, o_boff, o_zero;
     p->kperm.assign(kperm.begin(), kperm.end());
-    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, 0, 0, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
-                          &o_zero);
+    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, 0, 0, &blob, &o_hi, &o_lo, &o_mid, &o_idx,
+                          &o_boff, &o_zero);
     if (st != SS_OK) return st;
     st = upload(p, blob);
     if (st != SS_OK) return st;
@@ -531,8 +558,8 @@ ss_status plan_mma1d(ss_plan_ *p, int engine) {
     const std::vector<int> kperm = order_1d(gm, p->k, mode);
     p->kperm.assign(kperm.begin(), kperm.end());
     std::vector<uint8_t> blob;
-    size_t o_hi, o_lo, o_idx, o_boff, o_zero;
-    st = build_mma_tables(p, gm, kperm, mode, part, 1, 0, false, 0, 0, &blob, &o_hi, &o_lo, &o_idx, &o_boff,
+    size_t o_hi, o_lo, o_mid, o_idx, o_boff, o_zero;
+    st = build_mma_tables(p, gm, kperm, mode, part, 1, 0, false, 0, 0, &blob, &o_hi, &o_lo, &o_mid, &o_idx, &o_boff,
                           &o_zero);
     if (st != SS_OK) return st;
     const MmaLaunch fn = find_mma1d(p->rad, mode, part);
@@ -687,9 +714,11 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     p->info.r2 = o.r2;
 
     ss_status st = SS_E_UNSUPPORTED;
-    const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16 || dtype == SS_SPLIT_BF16;
+    const bool split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16 || dtype == SS_SPLIT_BF16 ||
+                       dtype == SS_SPLIT3_BF16;
     int engine = o.engine;
-    const bool split3 = split && dtype != SS_SPLIT_BF16;  // 3-D kernels take an FP32 state
+    // 3-D and 1-D kernels take an FP32 state
+    const bool split3 = split && dtype != SS_SPLIT_BF16 && dtype != SS_SPLIT3_BF16;
     const bool mma2 = split || dtype == SS_F16;   // state types of the 2-D matrix kernels
     if (mma2 && ndim == 2 && (engine == SS_ENGINE_AUTO || engine == SS_ENGINE_SMFMAC)) {
         st = plan_mma2d(p, SS_ENGINE_SMFMAC);
@@ -710,19 +739,26 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
         st = plan_mma2d_f64(p);
     }
     if (st != SS_OK && (engine == SS_ENGINE_DIRECT || engine == SS_ENGINE_AUTO) &&
-        (dtype == SS_F32 || dtype == SS_F64 || split) && o.r1 == 0)
+        (dtype == SS_F32 || dtype == SS_F64 || split) && dtype != SS_SPLIT3_BF16 && o.r1 == 0)
         st = plan_direct(p);
     if (st != SS_OK) {
         free_plan(p);
         return st;
     }
     if (edge_fused && !p->host_only) {
-        if (hipMalloc(&p->edge_w, p->w1.size() * sizeof(double)) != hipSuccess) {
+        // the unfused coefficients in FP64, then in FP32 (one allocation)
+        const size_t n = p->w1.size();
+        std::vector<uint8_t> blob(n * (sizeof(double) + sizeof(float)));
+        std::vector<float> w32(p->w1.begin(), p->w1.end());
+        std::memcpy(blob.data(), p->w1.data(), n * sizeof(double));
+        std::memcpy(blob.data() + n * sizeof(double), w32.data(), n * sizeof(float));
+        if (hipMalloc(&p->edge_w, blob.size()) != hipSuccess) {
             p->edge_w = nullptr;
             free_plan(p);
             return SS_E_NOMEM;
         }
-        if (hipMemcpy(p->edge_w, p->w1.data(), p->w1.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        p->edge_w32 = reinterpret_cast<float *>(p->edge_w + n);
+        if (hipMemcpy(p->edge_w, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess) {
             free_plan(p);
             return SS_E_DEVICE;
         }
@@ -746,7 +782,7 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     inf.engine = p->engine;
     inf.dtype = dtype;
     inf.boundary = p->boundary;
-    inf.launches_per_sweep = p->edge_rad && !(p->ndim == 1 && p->mma) ? 2 : 1;
+    inf.launches_per_sweep = p->edge_rad && !band_in_launch(p) ? 2 : 1;
     for (int d = 0; d < 3; ++d) inf.dims[d] = p->dims[d];
     // plans with the same class share device-table contents: their grids can
     // be swept by one launch
@@ -784,6 +820,16 @@ ss_status copy_out(const std::vector<T> &v, void *buf, size_t *nbytes) {
 }  // namespace
 
 namespace ss {
+// The band of a fused zero-halo sweep is computed inside the sweep launch by
+// the 1-D kernels and the 2-D matrix kernels (radius-1 sweeps, S <= 3, the
+// scratch those kernels hold); the 2-D direct engine uses a second launch.
+bool band_in_launch(const ss_plan_ *p) {
+    if (!p->mma || !p->edge_rad) return false;
+    if (p->ndim == 1) return true;
+    return p->ndim == 2 && p->engine != SS_ENGINE_DIRECT && p->edge_rad == 1 && p->fuse <= 3 &&
+           p->fuse * p->edge_rad <= 3;
+}
+
 // One sweep of the plan over n grids of its own shape class (same tables,
 // same boundary): one kernel launch.  dims_j = (nz, ny, nx) of grid j.
 hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *const *out,
@@ -802,16 +848,19 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
         a.njobs = n;
         for (int j = 0; j < n; ++j)
             a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
-        // the 1-D matrix kernels recompute the end bands in the same launch
-        if (p->ndim == 1 && p->edge_w) {
+        // the 1-D kernels and the 2-D matrix kernels recompute the band of a
+        // fused zero-halo sweep in the same launch
+        if (p->edge_w && band_in_launch(p)) {
             a.edge_w = p->edge_w;
+            a.edge_w32 = p->edge_w32;
             a.edge_rad = p->edge_rad;
             a.edge_steps = p->fuse;
         }
         e = p->mma(a, s);
-        if (p->ndim == 1) return e;
+        if (band_in_launch(p)) return e;
     }
-    // zero-halo fused sweeps: exact values for the band along the edges
+    // zero-halo fused sweeps of the 2-D direct engine: exact values for the
+    // band along the edges, by a second launch
     if (e != hipSuccess || !p->edge_w) return e;
     EdgeArgs ea{};
     ea.njobs = n;
@@ -928,6 +977,7 @@ ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *n
         case SS_Q_META: return copy_out(p->meta, buf, nbytes);
         case SS_Q_HI: return copy_out(p->hi, buf, nbytes);
         case SS_Q_LO: return copy_out(p->lo, buf, nbytes);
+        case SS_Q_MID: return copy_out(p->mid, buf, nbytes);
         case SS_Q_LUT: return copy_out(p->lut, buf, nbytes);
         case SS_Q_MODEL: return copy_out(p->model, buf, nbytes);
         case SS_Q_KERNEL_LUT: return copy_out(p->kernel_lut, buf, nbytes);

@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libsparstencil.so")
 SS_OK, SS_PENDING = 0, 1
 SS_E_INVALID, SS_E_UNSUPPORTED, SS_E_NOMEM, SS_E_DEVICE, SS_E_NOT_FOUND, SS_E_BUSY = -1, -2, -3, -4, -5, -6
 SHAPES = {"box": 0, "star": 1}
-DTYPES = {"f64": 0, "f32": 1, "f16": 2, "f32_split_f16": 3, "f32_split_bf16": 4, "split_bf16": 5}
+DTYPES = {"f64": 0, "f32": 1, "f16": 2, "f32_split_f16": 3, "f32_split_bf16": 4, "split_bf16": 5,
+          "split3_bf16": 6}
 BOUNDARIES = {"zero": 0, "periodic": 1}
 ENGINES = {"auto": 0, "smfmac": 1, "mfma": 2, "direct": 3}
 ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
-(Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM) = range(11)
+(Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM,
+ Q_MID) = range(12)
 
 EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
            "sparstencil_sweep", "sparstencil_sweep_batch", "sparstencil_launch_count", "sparstencil_grid_bytes",
@@ -305,7 +307,7 @@ class Plan:
         raw = sparstencil_plan_query(self.handle, what)
         dt = {Q_COEFFS: np.float64, Q_PERM: np.int32, Q_VALUES: np.float64, Q_META: np.uint8,
               Q_HI: np.uint16, Q_LO: np.uint16, Q_LUT: np.int32, Q_MODEL: np.float64,
-              Q_KERNEL_LUT: np.int32, Q_KERNEL_PERM: np.int32}[what]
+              Q_KERNEL_LUT: np.int32, Q_KERNEL_PERM: np.int32, Q_MID: np.uint16}[what]
         return np.frombuffer(raw, dtype=dt).copy()
 
     def run(self, inp, out, steps, stream=None):

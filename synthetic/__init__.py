@@ -128,6 +128,21 @@ def grid_bf16_planes(shape, seed: int = GRID_SEED) -> np.ndarray:
     return np.stack([hi_bits, lo_bits])
 
 
+def grid_bf16_planes3(shape, seed: int = GRID_SEED) -> np.ndarray:
+    """Three bf16 planes as uint16 bit patterns, shape (3, *shape): [hi,
+    mid, lo], each the top 16 bits of what the planes before it leave of
+    float32(x) (so hi + mid + lo = float32(x) exactly for these draws)."""
+    x = grid_f32(shape, seed)
+    out = []
+    rem = x.copy()
+    for _ in range(3):
+        bits = (rem.view(np.uint32) >> 16).astype(np.uint16)
+        val = (bits.astype(np.uint32) << 16).view(np.float32)
+        rem = (rem - val).astype(np.float32)
+        out.append(bits)
+    return np.stack(out)
+
+
 # ----------------------------------------------------------------------------
 # serving stream
 

@@ -247,7 +247,9 @@ def test_fusion_with_zero_halo(engine, shape, dims, fuse, steps):
     with native.Plan(shape, 1, w, dims, "f32_split_f16", boundary="zero", fuse_steps=fuse, engine=engine) as p:
         info = p.info
         assert info["engine_name"] == engine and info["fuse_steps"] == fuse and info["k"] == 2 * fuse + 1
-        assert info["launches_per_sweep"] == 2
+        # the matrix kernels recompute the band inside the sweep launch, the
+        # direct engine by a second launch
+        assert info["launches_per_sweep"] == (2 if engine == "direct" else 1)
         got = run_plan(p, x0, steps)
     ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=False)
     err = normwise_err(got, ref)

@@ -25,7 +25,7 @@ def kernels(asm: str):
     return out
 
 
-SOURCES = ["mma2d_f32_r1.hip", "mma2d_f32_r2.hip", "mma2d_f32_r3.hip", "mma2d_f16.hip", "mma2d_planes.hip", "mma3d.hip", "mma2d_f64.hip", "mma1d.hip", "direct2d.hip"]
+SOURCES = ["mma2d_f32_r1.hip", "mma2d_f32_r2.hip", "mma2d_f32_r3.hip", "mma2d_f16.hip", "mma2d_planes.hip", "mma2d_planes3.hip", "mma3d.hip", "mma2d_f64.hip", "mma1d.hip", "direct2d.hip"]
 
 
 @pytest.fixture(scope="module")

@@ -299,6 +299,31 @@ def test_split_reconstruction_bound(fmt, bound):
         assert abs(c - rec) <= bound * abs(c) + floor
 
 
+def test_three_part_split():
+    """Three-part bfloat16 split: every part a bfloat16 number, each the
+    rounding of what the parts before it leave (each at most 2^-8 of the one
+    before), so |c - (hi + mid + lo)| is at most half a bfloat16 spacing of
+    the last remainder (about 2^-27 |c|; asserted at 2^-26), and the sum
+    reproduces c exactly when c has 24 significant bits or fewer (an FP32
+    number).  Pinned by exact rational arithmetic."""
+    from fractions import Fraction
+    g = synthetic.rng(29)
+    vals = g.uniform(-1, 1, size=(30, 20)) * (2.0 ** g.integers(-6, 6, size=(30, 20)))
+    hi, mid, lo = T.split_three_bf16(vals)
+    for idx in np.ndindex(*vals.shape):
+        c = float(vals[idx])
+        parts = [fpformat.bf16_value(int(x[idx])) for x in (hi, mid, lo)]
+        assert abs(parts[1]) <= abs(parts[0]) * 2.0 ** -8 and abs(parts[2]) <= abs(parts[1]) * 2.0 ** -8
+        err = abs(Fraction(c) - sum(Fraction(v) for v in parts))
+        assert err <= Fraction(abs(c)) * Fraction(1, 2 ** 26)
+    # FP32 numbers split exactly
+    f32 = vals.astype(np.float32).astype(np.float64)
+    hi, mid, lo = T.split_three_bf16(f32)
+    for idx in np.ndindex(*f32.shape):
+        parts = [fpformat.bf16_value(int(x[idx])) for x in (hi, mid, lo)]
+        assert sum(Fraction(v) for v in parts) == Fraction(float(f32[idx]))
+
+
 def test_split_overflow_raises():
     with pytest.raises(OverflowError):
         T.split_hilo(np.array([70000.0]), "f16")

@@ -176,23 +176,74 @@ def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
         wk = p.table(native.Q_COEFFS).reshape(info["k"], info["k"])
     a, s, d = T.morph(wk, info["r1"], info["r2"])
     if engine == "smfmac":
-        ref = T.compact_sparse_order(a, T.group(T.plane_pairs(d)[0], 64), 64, d.g)
+        perm = T.group(T.plane_pairs(d)[0], 64)
+        _check_sparse_kernel_order(a, d, perm, got)
+        ref = T.compact_sparse_order(a, perm, 64, d.g)
     else:
         ref = T.compact_dense_order(a, 32)
-    assert np.array_equal(got, np.array(ref, dtype=np.int32))
+        assert np.array_equal(got, np.array(ref, dtype=np.int32))
     if shape == "star" and radius == 3:
-        assert len(ref) < (len(T.group(T.plane_pairs(d)[0], 64)) if engine == "smfmac" else -(-d.k_prime // 32) * 32)
+        assert len(got) < (len(T.group(T.plane_pairs(d)[0], 64)) if engine == "smfmac" else -(-d.k_prime // 32) * 32)
+        assert len(got) <= len(ref)
+
+
+def _check_sparse_kernel_order(a, d, perm, got):
+    """The sparse kernel order against the oracle: Algorithm 1's kept groups
+    first, bit for bit; then the re-paired dominoes, each group two
+    compatible aligned dominoes (or one and a zero domino), every used
+    column exactly once, and as few groups as a maximum matching of the
+    dominoes' compatibility graph gives (networkx, not the planner's
+    matcher)."""
+    kept, best = T.max_repairing_groups(a, perm, d.g)
+    got = [int(c) for c in got]
+    nk = 4 * len(kept)
+    assert got[:nk] == [c for grp in kept for c in grp]
+    groups = [tuple(got[j:j + 4]) for j in range(nk, len(got), 4) if any(c != T.ZETA for c in got[j:j + 4])]
+    assert len(groups) == best
+    for c0, c1, c2, c3 in groups:
+        assert c1 == c0 + 1 and (c0 % d.g) % 2 == 0
+        assert (c2 == T.ZETA and c3 == T.ZETA) or (c3 == c2 + 1 and (c2 % d.g) % 2 == 0)
+        assert T.dominoes_compatible(a, (c0, c1), (c2, c3))
+    used = set(int(c) for c in np.flatnonzero(T.used_columns(a)))
+    cols = [c for c in got if c != T.ZETA]
+    assert len(cols) == len(set(cols)) and used <= set(cols)
+    for j in range(0, len(got), 4):
+        c4 = [c for c in got[j:j + 4] if c != T.ZETA]
+        assert np.all(np.count_nonzero(a[:, c4], axis=1) <= 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("r1,r2", [(8, 8), (8, 4), (16, 2), (8, 2)])
+def test_repairing_is_a_maximum_matching(seed, r1, r2):
+    """Radius-3 stencils with random zero patterns (about half the box):
+    the sparse kernel order re-pairs the set-aside dominoes by a maximum
+    matching (the paper's general matcher, Section 3.2), checked against
+    networkx on the same graph; completeness and 2:4 validity by brute
+    force on A'."""
+    rng = np.random.default_rng(100 + seed)
+    w = rng.uniform(-1, 1, (7, 7))
+    w[rng.random((7, 7)) < 0.5] = 0.0
+    w[3, 3] = 1.0
+    dims = (64, 64)
+    with native.Plan("box", 3, w, dims, "f32_split_f16", engine="smfmac", r1=r1, r2=r2, host_only=True) as p:
+        got = p.table(native.Q_KERNEL_PERM)
+    a, s, d = T.morph(w, r1, r2)
+    _check_sparse_kernel_order(a, d, T.group(T.plane_pairs(d)[0], 64), got)
 
 
 def test_zero_halo_fusion_scope():
     """Fused sweeps with a zero halo: 2-D FP32-state plans only, S = 2 (any
-    radius) or S = 3 (radius 1), the band along the edges being a second
-    launch; planes, 3-D, S = 4 and S = 3 beyond radius 1 stay unsupported."""
+    radius) or S = 3 (radius 1), the band along the edges recomputed inside
+    the sweep launch by the matrix kernels and by a second launch on the
+    direct engine; planes, 3-D, S = 4 and S = 3 beyond radius 1 stay
+    unsupported."""
     w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
     with native.Plan("box", 1, w, (64, 64), "f32_split_bf16", fuse_steps=2, host_only=True) as p:
         info = p.info
-        assert info["fuse_steps"] == 2 and info["k"] == 5 and info["launches_per_sweep"] == 2
+        assert info["fuse_steps"] == 2 and info["k"] == 5 and info["launches_per_sweep"] == 1
     with native.Plan("box", 1, w, (64, 64), "f32_split_f16", fuse_steps=3, host_only=True) as p:
+        assert p.info["k"] == 7 and p.info["launches_per_sweep"] == 1
+    with native.Plan("box", 1, w, (64, 64), "f32_split_f16", fuse_steps=3, engine="direct", host_only=True) as p:
         assert p.info["k"] == 7 and p.info["launches_per_sweep"] == 2
     w3r, _ = synthetic.random_coeffs("box", 3, 2, seed=1, grid_shape=(64, 64))
     for rad, wr, dtype, fuse in [(1, w, "split_bf16", 2), (1, w, "f32_split_f16", 4), (3, w3r, "f32_split_f16", 3)]:
@@ -261,3 +312,42 @@ def test_direct_engine_refuses_radii_beyond_its_kernels():
     w6[6, :] = 1.0 / 13
     with native.Plan("box", 6, w6, (100, 100), "f32", engine="direct", host_only=True) as p:
         assert p.info["engine_name"] == "direct"
+
+
+@pytest.mark.parametrize("shape,seed,fuse", [("star", 45, 2), ("box", 277, 2), ("box", 3, 1)])
+def test_three_part_planes_tables(shape, seed, fuse):
+    """bfloat16 hi/mid/lo planes state: the canonical tables as for two
+    parts, the coefficients' hi, mid and lo parts bit-exact against the
+    oracle's three-part split, and the model with six products and three
+    planes."""
+    dims = (8192, 8192)
+    w, _ = synthetic.random_coeffs(shape, 3, 2, seed=seed, grid_shape=dims)
+    with native.Plan(shape, 3, w, dims, "split3_bf16", boundary="periodic", fuse_steps=fuse,
+                     engine="smfmac", host_only=True) as p:
+        info = p.info
+        assert info["passes"] == 6
+        wf = T.compose(w, fuse) if fuse > 1 else w
+        k = 7 if fuse == 1 else 13
+        a, s, d = T.morph(T.bounding_box("box", (k - 1) // 2, 2, wf), info["r1"], info["r2"])
+        perm = T.group(T.plane_pairs(d)[0], 64)
+        assert np.array_equal(p.table(native.Q_PERM), np.array(perm, dtype=np.int32))
+        vals, meta = T.compress(a, s, perm)
+        hi, mid, lo = T.split_three_bf16(vals)
+        assert np.array_equal(p.table(native.Q_HI), hi.reshape(-1))
+        assert np.array_equal(p.table(native.Q_MID), mid.reshape(-1))
+        assert np.array_equal(p.table(native.Q_LO), lo.reshape(-1))
+        rows = p.table(native.Q_MODEL).reshape(-1, 7)
+    cands = [(int(r[0]), int(r[1])) for r in rows]
+    best, table = T.explore(k, 2, dims, cands, elem_bytes=2, coef_bytes=2, passes=6, planes_state=3)
+    for r in rows:
+        assert r[2] == pytest.approx(table[(int(r[0]), int(r[1]))][0], rel=1e-12)
+    assert (info["r1"], info["r2"]) == best
+
+
+def test_three_part_planes_scope():
+    # matrix engines only, 2-D, rows a multiple of 8 values
+    w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
+    for kw in (dict(engine="direct"), dict(dims=(64, 60))):
+        dims = kw.pop("dims", (64, 64))
+        with pytest.raises(native.SparStencilError):
+            native.Plan("box", 1, w, dims, "split3_bf16", host_only=True, **kw)
