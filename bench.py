@@ -289,7 +289,8 @@ def workloads_leg(native, torch, stream):
     """The other workloads of the study on every engine that runs them:
     Heat-2D 256^2 FP64 (10 sweeps, zero halo), Star-2D13P / Box-2D49P on
     8192^2 bfloat16 hi+lo planes (50 sweeps, 2-step fusion, periodic),
-    Heat-3D / Box-3D27P on 512^3 FP32 (20 sweeps, zero halo) and 3- and
+    Heat-3D / Box-3D27P on 512^3 FP32 (20 sweeps, zero halo, one or two
+    sweeps per launch) and 3- and
     5-point 1-D stencils on 10,240,000 points (100 sweeps, zero halo, one or
     three sweeps per launch).  Returns the
     timings and, per result, the inputs and GPU values at sampled points for
@@ -352,13 +353,15 @@ def workloads_leg(native, torch, stream):
            lambda h: torch.from_numpy(h).to("cuda:0"), False, pts=sample_points_2d(NY, NX, 8),
            pick=lambda y, pt: float(y[pt].item()))
     del x16
-    # 3-D 512^3 FP32
+    # 3-D 512^3 FP32, one sweep per launch and two fused sweeps per launch
+    # (the band within one of a face recomputed in the same launch)
     x3 = synthetic.grid_f32((512, 512, 512), seed=0)
-    for name, shape, seed in [("heat3d7p_512_T20", "star", 29), ("box3d27p_512_T20", "box", 70)]:
+    for name, shape, seed, fuse in [("heat3d7p_512_T20", "star", 29, 1), ("box3d27p_512_T20", "box", 70, 1),
+                                    ("heat3d7p_512_S2_T20", "star", 29, 2), ("box3d27p_512_S2_T20", "box", 70, 2)]:
         w = synthetic.random_coeffs(shape, 1, 3, seed=seed)[0]
-        pts = [(0, 0, 0), (255, 100, 511), (511, 511, 3), (17, 300, 200)]
+        pts = [(0, 0, 0), (255, 100, 511), (511, 511, 3), (17, 300, 200), (0, 250, 250)]
         record(name, shape, 1, w, (512, 512, 512), "f32_split_f16", 20, ["smfmac", "mfma", "direct"], x3,
-               lambda h: torch.from_numpy(h).to("cuda:0"), False, pts=pts,
+               lambda h: torch.from_numpy(h).to("cuda:0"), False, fuse=fuse, pts=pts,
                pick=lambda y, pt: float(y[pt].item()))
     del x3
     # 1-D on the paper's 10,240,000-point grids: a 3-point (Heat-1D shape)
@@ -574,7 +577,7 @@ def profile_only(name: str, fuse: int):
     else:
         w = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
         x = torch.from_numpy(synthetic.grid_f32((512, 512, 512), seed=0)).to("cuda:0")
-        plan = native.Plan("box", 1, w, (512, 512, 512), "f32_split_f16", engine="smfmac")
+        plan = native.Plan("box", 1, w, (512, 512, 512), "f32_split_f16", engine="smfmac", fuse_steps=min(fuse, 2))
     y = torch.empty_like(x)
     # one device copy of the grid: a plain copy kernel of known size, which
     # calibrates the HBM byte counters
@@ -592,7 +595,7 @@ def profile_only(name: str, fuse: int):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the stencil path runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.profile:
         profile_only(args.profile, args.fuse)

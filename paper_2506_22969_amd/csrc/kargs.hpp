@@ -28,9 +28,6 @@ struct MmaArgs {
     int njobs;
     int total_items;         // work items over all jobs
     int nxcd;                // XCDs the launch's workgroups are dealt over
-    int item_wgs;            // workgroups that sweep work items (2-D matrix
-                             // kernels; the launch's other workgroups compute
-                             // the band of a fused zero-halo sweep)
     MmaJob job[kMaxJobs];
     int periodic;
     float inv_sigma;

@@ -270,12 +270,12 @@ __device__ inline float band_value(const float *in, int ny, int nx, int y, int x
 // paper Section 4.1 fuses three): the composed stencil applied to the
 // zero-padded grid is exact only farther than S - 1 from the edges, and the
 // products leave the points within that band (widened as BandBounds says)
-// unwritten.  Band workgroup w of nb (the launch's workgroups after the
-// item workgroups) computes an equal share of the band points of all grids
-// of the launch, each as S plain sweeps in FP32 (band_value) from the input
-// grid.  The band workgroups are dispatched last: they run on the compute
-// units the item workgroups leave as they finish.
+// unwritten.  Workgroup wg of nb computes, after its work items, an equal
+// share of the band points of all grids of the launch, each as S plain
+// sweeps in FP32 (band_value) from the input grid: about one point per
+// thread, so the band adds about one such evaluation to the launch's tail.
 __device__ inline void band_share(const MmaArgs &p, int wg, int nb) {
+    if (p.edge_steps < 2) return;
     float w[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -519,23 +519,20 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     char *conv = lds;
     auto stage = [&](int i) { return lds + C::CONV_BYTES + i * C::STAGE_ALLOC; };
 
-    if constexpr (STATE == kStateF32) {
-        if ((int)blockIdx.x >= p.item_wgs) {
-            band_share(p, (int)blockIdx.x - p.item_wgs, (int)gridDim.x - p.item_wgs);
-            return;
-        }
-    }
     const float sigma = 1.0f / p.inv_sigma;
     const float inv_sigma = p.inv_sigma;
     const int nxcd = p.nxcd;
-    const int nwg = p.item_wgs;
+    const int nwg = gridDim.x;
     const int xcd = blockIdx.x % nxcd;
     const int stride = nwg / nxcd + (xcd < nwg % nxcd ? 1 : 0);
     const int before = xcd * (nwg / nxcd) + min(xcd, nwg % nxcd);
     const int range_begin = (int)((long long)p.total_items * before / nwg);
     const int total = (int)((long long)p.total_items * (before + stride) / nwg);
     const int first = range_begin + blockIdx.x / nxcd;
-    if (first >= total) return;
+    if (first >= total) {
+        if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg);
+        return;
+    }
 
     // gather addresses of unit 0: the tile's patch origin in the converted
     // slab plus the plan's offset of each B register
@@ -609,6 +606,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     // the pipeline always runs NS items ahead: let those transfers land
     // before the workgroup's LDS is released
     wait_vmcnt<0>();
+    if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg);
 }
 
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE, bool VEC, int BC>
@@ -617,20 +615,8 @@ static hipError_t launch_c_bc(const MmaArgs &a, hipStream_t s) {
     if (const hipError_t e = device_shape(&cus, &xcds); e != hipSuccess) return e;
     MmaArgs b = a;
     b.nxcd = xcds;
-    b.item_wgs = a.total_items < cus ? a.total_items : cus;
-    // a fused zero-halo launch adds workgroups for the band, about two
-    // points per thread (a band has b rows at the top and at the bottom and
-    // at most 4 + b + 3 columns a row at the sides)
-    int band_wgs = 0;
-    if (STATE == kStateF32 && a.edge_steps > 1) {
-        const long long b = a.edge_rad * (a.edge_steps - 1);
-        long long pts = 0;
-        for (int j = 0; j < a.njobs; ++j) pts += 2 * b * a.job[j].nx + (b + 7) * (long long)a.job[j].ny;
-        const long long w = (pts + 2 * kThreads - 1) / (2 * kThreads);
-        band_wgs = (int)(w < 1 ? 1 : w > 4096 ? 4096 : w);
-    }
-    hipLaunchKernelGGL((k_mma2c<R1, R2, KC, RAD, MODE, PART, STATE, VEC, BC>), dim3(b.item_wgs + band_wgs),
-                       dim3(kThreads), 0, s, b);
+    const int wgs = a.total_items < cus ? a.total_items : cus;
+    hipLaunchKernelGGL((k_mma2c<R1, R2, KC, RAD, MODE, PART, STATE, VEC, BC>), dim3(wgs), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@
 
 namespace ss {
 
-template <int R1, int R2, int RAD, bool VEC, bool BAND = false>
+template <int R1, int R2, int RAD, bool VEC>
 struct Pipe3 {
     using G = Mma3Geom<R1, R2, RAD>;
     static constexpr int DRW = (G::SROWS + kWaves - 1) / kWaves;   // rows each wave loads per plane
@@ -29,8 +29,8 @@ struct Pipe3 {
     static constexpr int DMA_PER_ROW = VEC ? 2 : 5;
     static constexpr int D = DRW * DMA_PER_ROW;                    // VMEM loads per wave per plane
     // VMEM stores per wave per output plane: one 16-byte store per M block,
-    // or four 4-byte ones (rows not 16-byte aligned, or a band to leave out)
-    static constexpr int M = G::MB * (VEC && !BAND ? 1 : 4);
+    // or four 4-byte ones (rows not 16-byte aligned)
+    static constexpr int M = G::MB * (VEC ? 1 : 4);
     static constexpr int A = 2 * RAD;                              // steps before the first store
     // Step l waits for plane l + 1 (its B operands are gathered while the
     // matrix cores multiply plane l).  VMEM operations a wave has issued
@@ -102,6 +102,143 @@ __device__ inline int plane_off(const unsigned (&o2)[VPK / 2], int v, int l) {
     return (v & 1) ? (int)(w >> 16) : (int)(w & 0xffffu);
 }
 
+// The band of a fused zero-halo launch of two radius-1 sweeps (composed
+// into one radius-2 stencil): applied to the zero-padded grid, the composed
+// stencil is exact only at points at least one away from every face (paper
+// Section 4.1 fuses sweeps; recomputing the band keeps the zero-halo result
+// exact).  The band is cut into boxes one point thick: the first and last
+// planes in 8 x 64 (rows x columns) tiles; the first and last rows of the
+// planes between in 8 x 64 (planes x columns) tiles; the first and last
+// columns of the rows between in 8 x 64 (planes x rows) tiles.
+constexpr int kBandT = 8, kBandW = 64;
+
+struct BandBox {
+    int z0, y0, x0, ez, ey, ex;
+    int kind;                    // 0: plane tile, 1: row tile, 2: column tile
+};
+
+struct BandTiles3 {
+    int mz, my;                  // planes and rows strictly inside
+    int fz, fy, fx;              // faces of each kind: 1, or 2 if the grid is wider than 1
+    int tz, ty, tx;              // tiles per face of each kind
+    __device__ inline BandTiles3(int nz, int ny, int nx) {
+        mz = max(nz - 2, 0);
+        my = max(ny - 2, 0);
+        fz = min(nz, 2);
+        fy = min(ny, 2);
+        fx = min(nx, 2);
+        const int cx = (nx + kBandW - 1) / kBandW, czm = (mz + kBandT - 1) / kBandT;
+        tz = (ny + kBandT - 1) / kBandT * cx;
+        ty = czm * cx;
+        tx = czm * ((my + kBandW - 1) / kBandW);
+    }
+    __device__ inline int count() const { return fz * tz + fy * ty + fx * tx; }
+    __device__ inline BandBox box(int t, int nz, int ny, int nx) const {
+        const int cx = (nx + kBandW - 1) / kBandW;
+        if (t < fz * tz) {
+            const int f = t / tz, r = t % tz;
+            const int y0 = (r / cx) * kBandT, x0 = (r % cx) * kBandW;
+            return BandBox{f ? nz - 1 : 0, y0, x0, 1, min(kBandT, ny - y0), min(kBandW, nx - x0), 0};
+        }
+        t -= fz * tz;
+        if (t < fy * ty) {
+            const int f = t / ty, r = t % ty;
+            const int z0 = 1 + (r / cx) * kBandT, x0 = (r % cx) * kBandW;
+            return BandBox{z0, f ? ny - 1 : 0, x0, min(kBandT, mz + 1 - z0), 1, min(kBandW, nx - x0), 1};
+        }
+        t -= fy * ty;
+        const int f = t / tx, r = t % tx, cy = (my + kBandW - 1) / kBandW;
+        const int z0 = 1 + (r / cy) * kBandT, y0 = 1 + (r % cy) * kBandW;
+        return BandBox{z0, y0, f ? nx - 1 : 0, min(kBandT, mz + 1 - z0), min(kBandW, my + 1 - y0), 1, 2};
+    }
+};
+
+// Exact two-sweep values of one band box of at most EZ x EY x EX points
+// (FP32, fixed order): the inputs within two of the box into LDS (zero
+// outside the grid), the first-sweep values within one of the box (zero
+// outside the grid) into LDS, then the second sweep at the box's points.
+// Window shapes are compile-time, so index arithmetic is by constants.
+template <int EZ, int EY, int EX>
+__device__ inline void band_box(const MmaJob &g, const BandBox &bx, const float (&w)[27], float *lds) {
+    constexpr int WZ = EZ + 4, WY = EY + 4, WX = EX + 4, NW = WZ * WY * WX;
+    constexpr int MY = EY + 2, MX = EX + 2, NM = (EZ + 2) * MY * MX;
+    constexpr int NO = EZ * EY * EX;
+    static_assert(NW <= 4096 && NM <= 2048 && NO <= kThreads, "band windows");
+    const float *in = static_cast<const float *>(g.in);
+    float *win = lds, *mid = lds + 4096;
+    float v[(NW + kThreads - 1) / kThreads];
+#pragma unroll
+    for (int r = 0; r < (NW + kThreads - 1) / kThreads; ++r) {
+        const int i = threadIdx.x + r * kThreads;
+        const int k = i % WX, j = (i / WX) % WY, l = i / (WX * WY);
+        const int z = bx.z0 - 2 + l, y = bx.y0 - 2 + j, x = bx.x0 - 2 + k;
+        const bool ok = i < NW && z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
+        v[r] = ok ? in[((size_t)z * g.ny + y) * g.nx + x] : 0.f;
+    }
+#pragma unroll
+    for (int r = 0; r < (NW + kThreads - 1) / kThreads; ++r)
+        if (threadIdx.x + r * kThreads < NW) win[threadIdx.x + r * kThreads] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < (NM + kThreads - 1) / kThreads; ++r) {
+        const int i = threadIdx.x + r * kThreads;
+        if (i < NM) {
+            const int k = i % MX, j = (i / MX) % MY, l = i / (MX * MY);
+            const int z = bx.z0 - 1 + l, y = bx.y0 - 1 + j, x = bx.x0 - 1 + k;
+            float m = 0.f;
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx)
+                        m = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], win[((l + dz) * WY + j + dy) * WX + k + dx], m);
+            const bool ok = z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
+            mid[i] = ok ? m : 0.f;
+        }
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    const int k = i % EX, j = (i / EX) % EY, l = i / (EX * EY);
+    if (i < NO && l < bx.ez && j < bx.ey && k < bx.ex) {
+        float acc = 0.f;
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    acc = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], mid[((l + dz) * MY + j + dy) * MX + k + dx], acc);
+        static_cast<float *>(g.out)[((size_t)(bx.z0 + l) * g.ny + bx.y0 + j) * g.nx + bx.x0 + k] = acc;
+    }
+    // the next box reuses the windows
+    __syncthreads();
+}
+
+// Workgroup wg of nb computes, after its work items (its LDS free), the
+// band boxes wg, wg + nb, ... of all grids of a fused zero-halo launch.
+__device__ inline void band_share3(const MmaArgs &p, int wg, int nb, float *lds) {
+    if (p.edge_steps < 2) return;
+    float w[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) w[i] = p.edge_w32[i];
+    int total = 0;
+    for (int j = 0; j < p.njobs; ++j) total += BandTiles3(p.job[j].nz, p.job[j].ny, p.job[j].nx).count();
+    for (int t = wg; t < total; t += nb) {
+        int j = 0, l = t;
+        for (; j < p.njobs - 1; ++j) {
+            const int c = BandTiles3(p.job[j].nz, p.job[j].ny, p.job[j].nx).count();
+            if (l < c) break;
+            l -= c;
+        }
+        const MmaJob &g = p.job[j];
+        const BandBox bx = BandTiles3(g.nz, g.ny, g.nx).box(l, g.nz, g.ny, g.nx);
+        if (bx.kind == 0) band_box<1, kBandT, kBandW>(g, bx, w, lds);
+        else if (bx.kind == 1) band_box<kBandT, 1, kBandW>(g, bx, w, lds);
+        else band_box<kBandT, kBandW, 1>(g, bx, w, lds);
+    }
+}
+
 // Calls f(integral_constant<R>, l0 + R) for R = 0..N-1 while l0 + R < n.
 template <int R, int N, typename F>
 __device__ inline void unroll_steps(F &f, int l0, int n) {
@@ -113,7 +250,9 @@ __device__ inline void unroll_steps(F &f, int l0, int n) {
     }
 }
 
-template <int R1, int R2, int KC, int RAD, int MODE, int PART, bool VEC, int BC>
+// BAND: a fused zero-halo launch; the items leave the band (Band3) unwritten
+// and every workgroup computes a share of it after its items.
+template <int R1, int R2, int KC, int RAD, int MODE, int PART, bool VEC, int BC, bool BAND>
 __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     using G = Mma3Geom<R1, R2, RAD>;
     using P = Pipe3<R1, R2, RAD, VEC>;
@@ -129,6 +268,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     const float sigma = 1.0f / p.inv_sigma;
     const float inv_sigma = p.inv_sigma;
     const float *zf = static_cast<const float *>(p.zeros);
+    const int bnd = BAND ? p.edge_rad * (p.edge_steps - 1) : 0;
     // XCD-aware contiguous item ranges, as in the 2-D kernel
     const int nxcd = p.nxcd;
     const int nwg = gridDim.x;
@@ -207,15 +347,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
         const int rows_left = min(G::WGH, g.ny - Y0);
         const int xbase = X0 + nbc * 128 + tx_t * R1;
         // output plane z0 + l - 2*RAD + i accumulates at step l in slot
-        // (i + l) % NZ; hi*hi, hi*lo and lo*hi accumulate separately
-        f4 accm[NZ][MB], acc1[NZ][MB], acc2[NZ][MB];
+        // (i + l) % NZ; hi*hi in accm, hi*lo and lo*hi together in acc1
+        // (issued a whole pass over the plane offsets apart, so that no
+        // product waits for the one before it)
+        f4 accm[NZ][MB], acc1[NZ][MB];
 #pragma unroll
         for (int i = 0; i < NZ; ++i)
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 accm[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
                 acc1[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                acc2[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
         // B operands of two planes: the one multiplied and the next one
         unsigned bh[2][CPP][VPK], bl[2][CPP][VPK];
@@ -253,7 +394,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
             // step earlier, is multiplied by every plane offset
             gather(std::integral_constant<int, 1 - PB>{}, l + 1);
 #pragma unroll
-            for (int c = 0; c < CPP; ++c)
+            for (int c = 0; c < CPP; ++c) {
 #pragma unroll
                 for (int pz = 0; pz < NZ; ++pz)
 #pragma unroll
@@ -261,12 +402,22 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                         const int kc = pz * CPP + c, i = (NZ - 1 - pz + R) % NZ;
                         accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh[PB][c], accm[i][mb], aidx[mb][kc]);
                         acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl[PB][c], acc1[i][mb], aidx[mb][kc]);
-                        acc2[i][mb] = mma<MODE, PART>(alo[mb][kc], bh[PB][c], acc2[i][mb], aidx[mb][kc]);
                     }
+#pragma unroll
+                for (int pz = 0; pz < NZ; ++pz)
+#pragma unroll
+                    for (int mb = 0; mb < MB; ++mb) {
+                        const int kc = pz * CPP + c, i = (NZ - 1 - pz + R) % NZ;
+                        acc1[i][mb] = mma<MODE, PART>(alo[mb][kc], bh[PB][c], acc1[i][mb], aidx[mb][kc]);
+                    }
+            }
             // output plane z0 + l - 2*RAD (slot R) is complete
             if (l >= 2 * RAD) {
-                float *out = static_cast<float *>(g.out) + ((size_t)(z0 + l - 2 * RAD) * g.ny + Y0) * g.nx;
+                const int zo = z0 + l - 2 * RAD;
+                float *out = static_cast<float *>(g.out) + ((size_t)zo * g.ny + Y0) * g.nx;
                 const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
+                // band points (fused zero halo) are left to the band pass
+                const bool plane_ok = !BAND || (zo >= bnd && zo < g.nz - bnd);
 #pragma unroll
                 for (int mb = 0; mb < MB; ++mb) {
                     const int o = mb * 16 + 4 * q;
@@ -274,18 +425,35 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                     const int gx = xbase + o % R1;
                     float ys[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ys[i] = accm[R][mb][i] + (acc1[R][mb][i] + acc2[R][mb][i]) * inv_sigma;
-                    const bool row_ok = gyr < rows_left;
+                    for (int i = 0; i < 4; ++i) ys[i] = accm[R][mb][i] + acc1[R][mb][i] * inv_sigma;
+                    const bool row_ok =
+                        gyr < rows_left && plane_ok && (!BAND || (Y0 + gyr >= bnd && Y0 + gyr < g.ny - bnd));
+                    const int xlo = BAND ? bnd : 0, xhi = BAND ? g.nx - bnd : g.nx;
                     if constexpr (VEC) {
+                        // groups of four clear of the band's columns as one
+                        // 16-byte store; a group that straddles them stores
+                        // its other values one by one, under a branch: those
+                        // stores are outside the waits' count, which only
+                        // makes a wave that issues them wait longer
                         const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
                                         __float_as_uint(ys[3])};
-                        const unsigned o4 = row_ok && gx < g.nx ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
+                        const bool whole = gx >= xlo && gx + 4 <= xhi;
+                        const unsigned o4 = row_ok && whole ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
                         __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o4, 0, 0);
+                        if constexpr (BAND) {
+                            if (row_ok && !whole && gx < g.nx) {
+#pragma unroll
+                                for (int i = 0; i < 4; ++i)
+                                    if (gx + i >= xlo && gx + i < xhi)
+                                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc,
+                                                                              (unsigned)(gyr * g.nx + gx + i) * 4u, 0, 0);
+                            }
+                        }
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
                             const unsigned o1 =
-                                row_ok && gx + i < g.nx ? (unsigned)(gyr * g.nx + gx + i) * 4u : kOob;
+                                row_ok && gx + i >= xlo && gx + i < xhi ? (unsigned)(gyr * g.nx + gx + i) * 4u : kOob;
                             __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc, o1, 0, 0);
                         }
                     }
@@ -296,7 +464,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
             for (int mb = 0; mb < MB; ++mb) {
                 accm[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
                 acc1[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
-                acc2[R][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
         };
 #pragma unroll 1
@@ -307,6 +474,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
         wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
     }
+    if constexpr (BAND) band_share3(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
 }
 
 // Direct 3-D sweep on the vector ALUs (the same-box baseline without the
@@ -317,7 +485,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
 // time, with FP32 fused multiply-adds and coefficients from an LDS copy.
 constexpr int kD3Rows = 8;   // output rows per thread
 
-template <int RAD, bool VEC, int BC>
+template <int RAD, bool VEC, int BC, bool BAND>
 __global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
     using G = Mma3Geom<8, 4, RAD>;
     using P = Pipe3<8, 4, RAD, VEC>;
@@ -334,6 +502,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
     __shared__ float wl[NZ * NZ * NZ];
     const unsigned lds0 = lds_addr_of(lds);
     const float *zf = static_cast<const float *>(p.zeros);
+    const int bnd = BAND ? p.edge_rad * (p.edge_steps - 1) : 0;
 
     const int nxcd = p.nxcd;
     const int nwg = gridDim.x;
@@ -425,11 +594,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
                     for (int y = 0; y < kD3Rows; ++y) asm volatile("" : "+v"(acc[i][y]));
             }
             if (l >= 2 * RAD) {
-                float *out = static_cast<float *>(g.out) + ((size_t)(z0 + l - 2 * RAD) * g.ny + Y0) * g.nx;
+                const int zo = z0 + l - 2 * RAD;
+                float *out = static_cast<float *>(g.out) + ((size_t)zo * g.ny + Y0) * g.nx;
                 const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
+                // band points (fused zero halo) are left to the band pass
+                const bool col_ok = BAND ? zo >= bnd && zo < g.nz - bnd && gx >= bnd && gx < g.nx - bnd : gx < g.nx;
 #pragma unroll
                 for (int y = 0; y < kD3Rows; ++y) {
-                    const unsigned o = y0 + y < rows_left && gx < g.nx ? (unsigned)((y0 + y) * g.nx + gx) * 4u : kOob;
+                    const bool row_ok = y0 + y < rows_left && (!BAND || (Y0 + y0 + y >= bnd && Y0 + y0 + y < g.ny - bnd));
+                    const unsigned o = row_ok && col_ok ? (unsigned)((y0 + y) * g.nx + gx) * 4u : kOob;
                     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(acc[R][y]), orsrc, o, 0, 0);
                 }
             }
@@ -441,6 +614,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
         wait_vmcnt<0>();
         __builtin_amdgcn_s_barrier();
     }
+    if constexpr (BAND) band_share3(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
 }
 
 template <int RAD, bool VEC, int BC>
@@ -448,7 +622,13 @@ static hipError_t launch_lds3d_bc(const MmaArgs &a, int cus, int xcds, hipStream
     MmaArgs b = a;
     b.nxcd = xcds;
     const int g = a.total_items < cus ? a.total_items : cus;
-    hipLaunchKernelGGL((k_lds3d<RAD, VEC, BC>), dim3(g), dim3(kThreads), 0, s, b);
+    if constexpr (BC == kBcZero) {
+        if (a.edge_steps > 1) {
+            hipLaunchKernelGGL((k_lds3d<RAD, VEC, BC, true>), dim3(g), dim3(kThreads), 0, s, b);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_lds3d<RAD, VEC, BC, false>), dim3(g), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 
@@ -457,7 +637,14 @@ static hipError_t launch3_bc(const MmaArgs &a, int cus, int xcds, hipStream_t s)
     MmaArgs b = a;
     b.nxcd = xcds;
     const int g = a.total_items < cus ? a.total_items : cus;
-    hipLaunchKernelGGL((k_mma3d<R1, R2, KC, RAD, MODE, PART, VEC, BC>), dim3(g), dim3(kThreads), 0, s, b);
+    if constexpr (BC == kBcZero) {
+        if (a.edge_steps > 1) {
+            hipLaunchKernelGGL((k_mma3d<R1, R2, KC, RAD, MODE, PART, VEC, BC, true>), dim3(g), dim3(kThreads), 0, s,
+                               b);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_mma3d<R1, R2, KC, RAD, MODE, PART, VEC, BC, false>), dim3(g), dim3(kThreads), 0, s, b);
     return hipGetLastError();
 }
 
@@ -501,10 +688,18 @@ static hipError_t launch_mma3d(MmaArgs &a, hipStream_t s) {
 
 // Radius 1 (k = 3) at tile (8,4): every plane has 60 staircase columns,
 // padded to one 64-wide sparse chunk (K 192) or two 32-wide dense chunks
-// (K 192).
+// (K 192).  Radius 2 (two radius-1 sweeps composed) at tile (8,2): a plane
+// has 72 staircase columns; the union of the planes' used columns takes two
+// sparse or three dense chunks a plane for the 27-point box (K 640 / 480)
+// and one sparse or two dense chunks for the 7-point star, whose composed
+// planes use at most the 13 points of a radius-2 diamond (K 320 / 320).
 static const MmaEntry kTable3[] = {
-    SS_MMA3(8, 4, 3, 1, kSparse, kPartF16),  SS_MMA3(8, 4, 6, 1, kDense, kPartF16),
-    SS_MMA3(8, 4, 3, 1, kSparse, kPartBF16), SS_MMA3(8, 4, 6, 1, kDense, kPartBF16),
+    SS_MMA3(8, 4, 3, 1, kSparse, kPartF16),   SS_MMA3(8, 4, 6, 1, kDense, kPartF16),
+    SS_MMA3(8, 4, 3, 1, kSparse, kPartBF16),  SS_MMA3(8, 4, 6, 1, kDense, kPartBF16),
+    SS_MMA3(8, 2, 10, 2, kSparse, kPartF16),  SS_MMA3(8, 2, 15, 2, kDense, kPartF16),
+    SS_MMA3(8, 2, 5, 2, kSparse, kPartF16),   SS_MMA3(8, 2, 10, 2, kDense, kPartF16),
+    SS_MMA3(8, 2, 10, 2, kSparse, kPartBF16), SS_MMA3(8, 2, 15, 2, kDense, kPartBF16),
+    SS_MMA3(8, 2, 5, 2, kSparse, kPartBF16),  SS_MMA3(8, 2, 10, 2, kDense, kPartBF16),
 };
 
 MmaLaunch find_mma3d(const MmaKey &k) {

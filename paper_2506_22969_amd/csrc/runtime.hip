@@ -360,11 +360,15 @@ bool pairs_adjacent(const Geometry &gm, const std::vector<int> &perm) {
 }
 
 // 3-D MMA engines (FP32 state).  The kernel's K order keeps every input
-// plane in whole chunks: each plane's own pair list (the 2-D matching of its
-// block staircase) grouped and padded to 64 columns (sparse), or its columns
-// in natural order padded to a multiple of 32 (dense).  The canonical tables
-// (queries) are those of the plain 3-D reading: plane lists concatenated,
-// then grouped and padded once.
+// plane in whole chunks, one order for all planes (the kernel gathers an
+// input plane once for every plane offset): the 2-D order of a plane's block
+// staircase, compacted to the union of the columns any plane offset uses --
+// Algorithm 1's groups re-paired (sparse, 64-column chunks) or the used
+// column pairs (dense, 32-column chunks).  A 27-point box uses every
+// column; a 7-point star composed over two sweeps uses at most a radius-2
+// diamond in any plane, which takes half the sparse chunks.  The canonical
+// tables (queries) are those of the plain 3-D reading: plane lists
+// concatenated, then grouped and padded once.
 ss_status plan_mma3d(ss_plan_ *p, int engine) {
     const int part = p->dtype == SS_F32_SPLIT_F16 ? kPartF16 : kPartBF16;
     const int mode = engine == SS_ENGINE_SMFMAC ? kSparse : kDense;
@@ -378,15 +382,20 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
         if (p->info.r1 && (c.r1 != p->info.r1 || c.r2 != p->info.r2)) continue;
         const Geometry g2 = make_geometry(2, p->k, c.r1, c.r2);
         const int plane = g2.m_b * g2.g, cpp = c.kc / p->k;
-        std::vector<int> one;
-        if (mode == kSparse) {
-            one = group_pairs(matrix_pairs(g2), 64);
-            if (!pairs_adjacent(g2, one) || (int)one.size() != 64 * cpp) continue;
-        } else {
-            if (g2.g % 2 || cpp * 32 < plane || (cpp - 1) * 32 >= plane) continue;
-            for (int x = 0; x < cpp * 32; ++x) one.push_back(x < plane ? x : kZeta);
-            if ((int)one.size() != 32 * cpp) continue;
+        if (mode == kDense && g2.g % 2) continue;
+        // |A'| summed over the plane offsets: nonzero where any plane is
+        const size_t kk = (size_t)p->k * p->k;
+        std::vector<double> u((size_t)g2.m_prime() * plane, 0.0);
+        for (int pz = 0; pz < p->k; ++pz) {
+            std::vector<double> wz(p->w.begin() + pz * kk, p->w.begin() + (pz + 1) * kk);
+            for (double &v : wz) v = std::fabs(v);
+            const std::vector<double> a = morph_matrix(g2, wz);
+            for (size_t i = 0; i < u.size(); ++i) u[i] += a[i];
         }
+        const std::vector<int> one = mode == kSparse ? compact_groups(g2, u, group_pairs(matrix_pairs(g2), 64), 64)
+                                                     : dense_order(g2, u, 32);
+        if (mode == kSparse && !pairs_adjacent(g2, one)) continue;
+        if ((int)one.size() != (mode == kSparse ? 64 : 32) * cpp) continue;
         kperm.clear();
         for (int pz = 0; pz < p->k; ++pz)
             for (int x : one) kperm.push_back(x == kZeta ? kZeta : x + pz * plane);
@@ -601,8 +610,8 @@ ss_status plan_direct(ss_plan_ *p) {
     if (!f64 && p->ndim == 3 && state == kStateF32 && slab_offsets_fit(p)) lds = find_lds_direct3d(p->rad);
     if (!f64 && p->ndim == 1 && state == kStateF32) lds = find_lds_direct1d(p->rad);
     if (!lds && p->rad > kDirectMaxRad) return SS_E_UNSUPPORTED;
-    // a fused zero-halo 1-D sweep needs the staged kernel's end-band workgroup
-    if (!lds && p->ndim == 1 && p->edge_rad) return SS_E_UNSUPPORTED;
+    // a fused zero-halo 1-D or 3-D sweep needs the staged kernel's band pass
+    if (!lds && p->ndim != 2 && p->edge_rad) return SS_E_UNSUPPORTED;
     const size_t wbytes = p->w.size() * (f64 ? 8 : 4);
     const size_t o_zero = (wbytes + 255) & ~(size_t)255;
     std::vector<uint8_t> blob(o_zero + 1024, 0);
@@ -656,12 +665,14 @@ ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs,
     if (o.fuse_steps < 1 || o.fuse_steps > 8) return SS_E_INVALID;
     if (o.engine < SS_ENGINE_AUTO || o.engine > SS_ENGINE_DIRECT) return SS_E_INVALID;
     if ((o.r1 == 0) != (o.r2 == 0) || o.r1 < 0 || o.r2 < 0) return SS_E_INVALID;
-    // a zero halo fuses 2-D sweeps of an FP32 state (two of any radius, or
-    // three of radius 1), with the band along the edges recomputed (the
-    // composed stencil is exact only farther than r(S-1) from the edges)
+    // a zero halo fuses sweeps of an FP32 state -- 2-D: two of any radius,
+    // or three of radius 1; 3-D: two of radius 1; 1-D: r*S <= 8 -- with the
+    // band along the edges recomputed (the composed stencil is exact only
+    // farther than r(S-1) from the edges)
     const bool edge_fused = o.fuse_steps > 1 && o.boundary == SS_BC_ZERO;
     const bool f32_split = dtype == SS_F32_SPLIT_F16 || dtype == SS_F32_SPLIT_BF16;
     if (edge_fused && !(f32_split && ((ndim == 2 && (o.fuse_steps == 2 || (o.fuse_steps == 3 && radius == 1))) ||
+                                      (ndim == 3 && o.fuse_steps == 2 && radius == 1) ||
                                       (ndim == 1 && radius * o.fuse_steps <= 8))))
         return SS_E_UNSUPPORTED;
     if (o.fuse_steps > 1 && !allow_fuse) return SS_E_INVALID;
@@ -821,13 +832,13 @@ ss_status copy_out(const std::vector<T> &v, void *buf, size_t *nbytes) {
 
 namespace ss {
 // The band of a fused zero-halo sweep is computed inside the sweep launch by
-// the 1-D kernels and the 2-D matrix kernels (radius-1 sweeps, S <= 3, the
-// scratch those kernels hold); the 2-D direct engine uses a second launch.
+// the 1-D and 3-D kernels and the 2-D matrix kernels (radius-1 sweeps,
+// S <= 3); the 2-D direct engine, and 2-D sweeps of larger radius, use a
+// second launch.
 bool band_in_launch(const ss_plan_ *p) {
     if (!p->mma || !p->edge_rad) return false;
-    if (p->ndim == 1) return true;
-    return p->ndim == 2 && p->engine != SS_ENGINE_DIRECT && p->edge_rad == 1 && p->fuse <= 3 &&
-           p->fuse * p->edge_rad <= 3;
+    if (p->ndim != 2) return true;
+    return p->engine != SS_ENGINE_DIRECT && p->edge_rad == 1 && p->fuse <= 3;
 }
 
 // One sweep of the plan over n grids of its own shape class (same tables,
@@ -848,8 +859,8 @@ hipError_t sweep_grids(const ss_plan_ *p, int n, const void *const *in, void *co
         a.njobs = n;
         for (int j = 0; j < n; ++j)
             a.job[j] = MmaJob{in[j], out[j], (int)dims[j][1], (int)dims[j][2], 0, (int)dims[j][0], 0};
-        // the 1-D kernels and the 2-D matrix kernels recompute the band of a
-        // fused zero-halo sweep in the same launch
+        // the 1-D and 3-D kernels and the 2-D matrix kernels recompute the
+        // band of a fused zero-halo sweep in the same launch
         if (p->edge_w && band_in_launch(p)) {
             a.edge_w = p->edge_w;
             a.edge_w32 = p->edge_w32;

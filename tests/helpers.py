@@ -33,9 +33,11 @@ def split_step_bound(fmt: str, n_mma: int) -> float:
     return 3 * u * u + (n_mma + 1) * 2.0 ** -24
 
 
-def apriori_bound(info: dict, w: np.ndarray, steps: int, dtype: str) -> float:
+def apriori_bound(info: dict, w: np.ndarray, steps: int, dtype: str, k_kernel: int = 0) -> float:
     """A-priori normwise bound after `steps` sweeps of a plan (info is the
-    plan's info dict, w the unfused coefficients).
+    plan's info dict, w the unfused coefficients; k_kernel, when given, the
+    length of the launched kernel's K order, which the 3-D kernels pad per
+    plane beyond the canonical K_pad).
 
     Per launch: the split bound of the engine's MMA count times sum|c| of the
     coefficients the launch applies (composed for fused launches); the direct
@@ -58,7 +60,7 @@ def apriori_bound(info: dict, w: np.ndarray, steps: int, dtype: str) -> float:
         else:
             fmt = "f16" if dtype == "f32_split_f16" else "bf16"
             chunk = 64 if eng == "smfmac" else 32
-            b = split_step_bound(fmt, 3 * int(info["k_pad"]) // chunk) * s
+            b = split_step_bound(fmt, 3 * max(int(info["k_pad"]), k_kernel) // chunk) * s
         return b + (U_BF16 ** 2 if dtype == "split_bf16" else 0.0)
 
     return (steps // fuse) * per_launch(ws) + (steps % fuse) * per_launch(w)

@@ -132,3 +132,79 @@ def test_3d_c4_full_size_sampled(shape):
     assert err <= tol
     # the split path's stated 1e-6 (measured 2e-7 Heat-3D, 6e-7 Box-3D27P)
     assert err <= STATED_SPLIT
+
+
+FUSED_CASES = [  # (shape, dims, steps): ragged, 4-byte rows, tiny (all band), z chunks
+    ("star", (20, 40, 264), 4),
+    ("box", (20, 40, 264), 5),
+    ("box", (7, 33, 129), 4),
+    ("star", (3, 5, 7), 2),
+    ("box", (64, 256, 512), 4),
+]
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
+@pytest.mark.parametrize("shape,dims,steps", FUSED_CASES)
+def test_3d_fused_zero_halo(engine, shape, dims, steps):
+    """Two radius-1 sweeps composed into one radius-2 launch on a zero halo:
+    the products (or the direct radius-2 sweep) away from the faces and the
+    exact two-sweep band within one of a face, in the same launch; against
+    the unfused FP64 oracle.  Odd step counts end with an unfused sweep."""
+    from .helpers import apriori_bound
+    w = coeffs(shape)
+    x0 = synthetic.grid_f32(dims, seed=11)
+    with native.Plan(shape, 1, w, dims, "f32_split_f16", fuse_steps=2, engine=engine) as p:
+        info = p.info
+        assert info["engine_name"] == engine and info["k"] == 5 and info["launches_per_sweep"] == 1
+        kk = len(p.table(native.Q_KERNEL_PERM))
+        got = run_plan(p, x0, steps)
+    ref = oracle_direct.run(x0.astype(np.float64), w, steps)
+    err = normwise_err(got, ref)
+    tol = apriori_bound(info, w, steps, "f32_split_f16", kk)
+    print(f"{engine} {shape} {dims} S=2 T={steps} err={err:.3e} tol={tol:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma"])
+@pytest.mark.parametrize("shape", ["star", "box"])
+def test_3d_fused_periodic_bf16(engine, shape):
+    """Fused radius-2 launches on a periodic grid (no band) with bfloat16
+    parts."""
+    from .helpers import apriori_bound
+    w = coeffs(shape)
+    dims = (24, 48, 264)
+    x0 = synthetic.grid_f32(dims, seed=12)
+    with native.Plan(shape, 1, w, dims, "f32_split_bf16", fuse_steps=2, boundary="periodic", engine=engine) as p:
+        info = p.info
+        kk = len(p.table(native.Q_KERNEL_PERM))
+        got = run_plan(p, x0, 4)
+    ref = oracle_direct.run(x0.astype(np.float64), w, 4, periodic=True)
+    err = normwise_err(got, ref)
+    tol = apriori_bound(info, w, 4, "f32_split_bf16", kk)
+    print(f"{engine} {shape} periodic bf16 S=2 err={err:.3e} tol={tol:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("shape", ["star", "box"])
+def test_3d_c4_fused_full_size_sampled(shape):
+    """C4 shapes (512^3, 20 sweeps, zero halo) with two sweeps per launch on
+    the sparse engine, sampled through dependency cones; corners and faces
+    are among the points (band values)."""
+    from .helpers import apriori_bound
+    dims = (512, 512, 512)
+    steps = 20
+    w = coeffs(shape)
+    x0 = synthetic.grid_f32(dims, seed=0)
+    with native.Plan(shape, 1, w, dims, "f32_split_f16", fuse_steps=2) as p:
+        info = p.info
+        assert info["engine_name"] == "smfmac" and info["fuse_steps"] == 2
+        kk = len(p.table(native.Q_KERNEL_PERM))
+        got = run_plan(p, x0, steps)
+    pts = sample_points3(*dims, 12, seed=4) + [(0, 200, 300), (511, 3, 0), (100, 0, 511), (255, 511, 256)]
+    ref = cone_sample(x0, w, steps, pts)
+    vals = np.array([got[pt] for pt in pts], dtype=np.float64)
+    err = float(np.abs(vals - ref).max() / np.abs(ref).max())
+    tol = apriori_bound(info, w, steps, "f32_split_f16", kk)
+    print(f"C4 fused {shape} sampled err={err:.3e} tol={tol:.3e}")
+    assert err <= tol
+    assert err <= STATED_SPLIT

@@ -232,10 +232,11 @@ def test_repairing_is_a_maximum_matching(seed, r1, r2):
 
 
 def test_zero_halo_fusion_scope():
-    """Fused sweeps with a zero halo: 2-D FP32-state plans only, S = 2 (any
+    """Fused sweeps with a zero halo: FP32-state plans only; 2-D S = 2 (any
     radius) or S = 3 (radius 1), the band along the edges recomputed inside
     the sweep launch by the matrix kernels and by a second launch on the
-    direct engine; planes, 3-D, S = 4 and S = 3 beyond radius 1 stay
+    direct engine; 3-D S = 2 of radius 1, the band inside the launch; planes,
+    S = 4, 2-D S = 3 beyond radius 1 and 3-D beyond S = 2 or radius 1 stay
     unsupported."""
     w, _ = synthetic.random_coeffs("box", 1, 2, seed=1, grid_shape=(64, 64))
     with native.Plan("box", 1, w, (64, 64), "f32_split_bf16", fuse_steps=2, host_only=True) as p:
@@ -249,9 +250,54 @@ def test_zero_halo_fusion_scope():
     for rad, wr, dtype, fuse in [(1, w, "split_bf16", 2), (1, w, "f32_split_f16", 4), (3, w3r, "f32_split_f16", 3)]:
         with pytest.raises(native.SparStencilError):
             native.Plan("box", rad, wr, (64, 64), dtype, fuse_steps=fuse, host_only=True)
+    # 3-D: two radius-1 sweeps, the band inside the launch on every engine
     w3, _ = synthetic.random_coeffs("box", 1, 3, seed=1)
+    for engine in ("smfmac", "mfma", "direct"):
+        with native.Plan("box", 1, w3, (8, 8, 8), "f32_split_f16", fuse_steps=2, engine=engine, host_only=True) as p:
+            assert p.info["k"] == 5 and p.info["launches_per_sweep"] == 1
+    for fuse, dtype in [(3, "f32_split_f16"), (2, "split_bf16")]:
+        with pytest.raises(native.SparStencilError):
+            native.Plan("box", 1, w3, (8, 8, 8), dtype, fuse_steps=fuse, host_only=True)
+    w3r2, _ = synthetic.random_coeffs("box", 2, 3, seed=1)
     with pytest.raises(native.SparStencilError):
-        native.Plan("box", 1, w3, (8, 8, 8), "f32_split_f16", fuse_steps=2, host_only=True)
+        native.Plan("box", 2, w3r2, (8, 8, 8), "f32_split_f16", fuse_steps=2, host_only=True)
+
+
+@pytest.mark.parametrize("shape,fuse,engine,k_pad", [
+    ("box", 2, "smfmac", 640), ("star", 2, "smfmac", 320), ("box", 2, "mfma", 480), ("star", 2, "mfma", 320),
+    ("star", 1, "smfmac", 192), ("box", 1, "smfmac", 192), ("star", 1, "mfma", 192)])
+def test_3d_kernel_order_is_the_union_order(shape, fuse, engine, k_pad):
+    """3-D kernel K order: one 2-D order for every plane (the kernel gathers
+    an input plane once for all plane offsets), compacted to the union of
+    the columns the planes of A' use -- the oracle's compaction of the
+    summed |A'| planes (sparse: Algorithm 1's groups re-paired, checked as
+    the 2-D orders are; dense: the used column pairs), each plane a valid
+    2:4 layout of its own block."""
+    w, _ = synthetic.random_coeffs(shape, 1, 3, seed=29 if shape == "star" else 70)
+    kw = dict(fuse_steps=fuse) if fuse > 1 else {}
+    with native.Plan(shape, 1, w, (40, 48, 264), "f32_split_f16", engine=engine, host_only=True, **kw) as p:
+        info = p.info
+        got = p.table(native.Q_KERNEL_PERM)
+        wk = p.table(native.Q_COEFFS).reshape((info["k"],) * 3)
+    k = info["k"]
+    assert len(got) == k_pad
+    planes = [T.morph(wk[pz], info["r1"], info["r2"]) for pz in range(k)]
+    d = planes[0][2]
+    plane = d.m_b * d.g
+    union = sum(np.abs(a) for a, _, _ in planes)
+    one = got[:len(got) // k]
+    for pz in range(k):
+        blk = got[pz * len(one):(pz + 1) * len(one)]
+        assert np.array_equal(blk, np.where(one >= 0, one + pz * plane, one))
+        a = planes[pz][0]
+        for j in range(0, len(one), 4):
+            cols = [int(c) for c in one[j:j + 4] if c >= 0]
+            if engine == "smfmac":
+                assert np.all(np.count_nonzero(a[:, cols], axis=1) <= 2)
+    if engine == "smfmac":
+        _check_sparse_kernel_order(union, d, T.group(T.plane_pairs(d)[0], 64), one)
+    else:
+        assert np.array_equal(one, np.array(T.compact_dense_order(union, 32), dtype=np.int32))
 
 
 @pytest.mark.parametrize("radius,fuse", [(1, 1), (2, 1), (1, 3), (2, 3), (4, 2), (8, 1)])
