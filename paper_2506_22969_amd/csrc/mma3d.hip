@@ -46,7 +46,8 @@ struct Pipe3 {
 };
 
 // Issue the transfers of input plane z (already wrapped; outside the grid
-// with a zero halo) into a ring slot.  Every wave moves the slab rows wave,
+// with a zero halo) into a ring slot.  Values outside a zero-halo grid come
+// from the 1 KiB zero block, each lane from its own part of it.  Every wave moves the slab rows wave,
 // wave + 8, ... (clamped to the last row, so that all waves issue the same
 // count); rows are item constants, passed as element offsets (-1: outside
 // the grid) with the slab row addresses.
@@ -68,8 +69,8 @@ __device__ inline void issue_plane(const MmaJob &g, const float *zf, unsigned sl
         for (int d = 0; d < P::DRW; ++d) {
             const bool row_ok = z_ok && row_off[d] >= 0;
             const float *row = in + row_off[d];
-            lds_dma16(row_ok && oka ? row + gxa : zf, slot_lds + row_lds[d]);
-            if (lane < 2) lds_dma16(row_ok && okb ? row + gxb : zf, slot_lds + row_lds[d] + 1024);
+            lds_dma16(row_ok && oka ? row + gxa : zf + 4 * lane, slot_lds + row_lds[d]);
+            if (lane < 2) lds_dma16(row_ok && okb ? row + gxb : zf + 4 * lane, slot_lds + row_lds[d] + 1024);
         }
     } else {
 #pragma unroll
@@ -80,12 +81,12 @@ __device__ inline void issue_plane(const MmaJob &g, const float *zf, unsigned sl
             for (int h = 0; h < 4; ++h) {
                 const int gx = wrap<BC>(X0 - 4 + 64 * h + lane, g.nx);
                 const bool ok = BC != kBcZero || (gx >= 0 && gx < g.nx);
-                lds_dma4(row_ok && ok ? row + gx : zf, slot_lds + row_lds[d] + 256 * h);
+                lds_dma4(row_ok && ok ? row + gx : zf + lane, slot_lds + row_lds[d] + 256 * h);
             }
             if (lane < 8) {
                 const int gx = wrap<BC>(X0 + 252 + lane, g.nx);
                 const bool ok = BC != kBcZero || (gx >= 0 && gx < g.nx);
-                lds_dma4(row_ok && ok ? row + gx : zf, slot_lds + row_lds[d] + 1024);
+                lds_dma4(row_ok && ok ? row + gx : zf + lane, slot_lds + row_lds[d] + 1024);
             }
         }
     }
@@ -153,54 +154,83 @@ struct BandTiles3 {
     }
 };
 
-// Exact two-sweep values of one band box of at most EZ x EY x EX points
-// (FP32, fixed order): the inputs within two of the box into LDS (zero
-// outside the grid), the first-sweep values within one of the box (zero
-// outside the grid) into LDS, then the second sweep at the box's points.
-// Window shapes are compile-time, so index arithmetic is by constants.
+// Exact two-sweep values of band boxes of at most EZ x EY x EX points
+// (FP32, fixed order): the inputs within two of a box (zero outside the
+// grid) are loaded into registers (band_load, one box ahead of the
+// arithmetic), then put into LDS; the first-sweep values within one of the
+// box (zero outside the grid) go to LDS; then the second sweep at the box's
+// points (band_compute).  Window shapes are compile-time, so index
+// arithmetic is by constants.
 template <int EZ, int EY, int EX>
-__device__ inline void band_box(const MmaJob &g, const BandBox &bx, const float (&w)[27], float *lds) {
-    constexpr int WZ = EZ + 4, WY = EY + 4, WX = EX + 4, NW = WZ * WY * WX;
-    constexpr int MY = EY + 2, MX = EX + 2, NM = (EZ + 2) * MY * MX;
-    constexpr int NO = EZ * EY * EX;
-    static_assert(NW <= 4096 && NM <= 2048 && NO <= kThreads, "band windows");
+struct BandWin {
+    static constexpr int WZ = EZ + 4, WY = EY + 4, WX = EX + 4, NW = WZ * WY * WX;
+    static constexpr int MY = EY + 2, MX = EX + 2, NM = (EZ + 2) * MY * MX;
+    static constexpr int NO = EZ * EY * EX;
+    static constexpr int NR = (NW + kThreads - 1) / kThreads;     // window values per thread
+    static_assert(NW <= 4096 && NM <= 2048 && NO <= kThreads && NR <= 8, "band windows");
+};
+
+template <int EZ, int EY, int EX>
+__device__ inline void band_load(const MmaJob &g, const BandBox &bx, float (&v)[8]) {
+    using B = BandWin<EZ, EY, EX>;
     const float *in = static_cast<const float *>(g.in);
-    float *win = lds, *mid = lds + 4096;
-    float v[(NW + kThreads - 1) / kThreads];
 #pragma unroll
-    for (int r = 0; r < (NW + kThreads - 1) / kThreads; ++r) {
+    for (int r = 0; r < B::NR; ++r) {
         const int i = threadIdx.x + r * kThreads;
-        const int k = i % WX, j = (i / WX) % WY, l = i / (WX * WY);
+        const int k = i % B::WX, j = (i / B::WX) % B::WY, l = i / (B::WX * B::WY);
         const int z = bx.z0 - 2 + l, y = bx.y0 - 2 + j, x = bx.x0 - 2 + k;
-        const bool ok = i < NW && z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
+        const bool ok = i < B::NW && z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
         v[r] = ok ? in[((size_t)z * g.ny + y) * g.nx + x] : 0.f;
     }
+}
+
+template <int EZ, int EY, int EX>
+__device__ inline void band_compute(const MmaJob &g, const BandBox &bx, const float (&v)[8], const float (&w)[27],
+                                    float *lds) {
+    using B = BandWin<EZ, EY, EX>;
+    float *win = lds, *mid = lds + 4096;
 #pragma unroll
-    for (int r = 0; r < (NW + kThreads - 1) / kThreads; ++r)
-        if (threadIdx.x + r * kThreads < NW) win[threadIdx.x + r * kThreads] = v[r];
+    for (int r = 0; r < B::NR; ++r)
+        if (threadIdx.x + r * kThreads < B::NW) win[threadIdx.x + r * kThreads] = v[r];
     __syncthreads();
+    // first-sweep values: threads take them with the window's thin axis
+    // slowest, so that a wave's values outside the grid (a whole layer of
+    // the thin axis) are skipped together
+    constexpr int MZ = EZ + 2;
 #pragma unroll
-    for (int r = 0; r < (NM + kThreads - 1) / kThreads; ++r) {
+    for (int r = 0; r < (B::NM + kThreads - 1) / kThreads; ++r) {
         const int i = threadIdx.x + r * kThreads;
-        if (i < NM) {
-            const int k = i % MX, j = (i / MX) % MY, l = i / (MX * MY);
+        if (i < B::NM) {
+            int l, j, k;
+            if constexpr (EX == 1) {
+                k = i / (MZ * B::MY);
+                j = i % B::MY;
+                l = (i / B::MY) % MZ;
+            } else {
+                k = i % B::MX;
+                j = (i / B::MX) % B::MY;
+                l = i / (B::MX * B::MY);
+            }
             const int z = bx.z0 - 1 + l, y = bx.y0 - 1 + j, x = bx.x0 - 1 + k;
-            float m = 0.f;
-#pragma unroll
-            for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx)
-                        m = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], win[((l + dz) * WY + j + dy) * WX + k + dx], m);
             const bool ok = z >= 0 && z < g.nz && y >= 0 && y < g.ny && x >= 0 && x < g.nx;
-            mid[i] = ok ? m : 0.f;
+            float m = 0.f;
+            if (ok) {
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+                            m = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx],
+                                               win[((l + dz) * B::WY + j + dy) * B::WX + k + dx], m);
+            }
+            mid[(l * B::MY + j) * B::MX + k] = m;
         }
     }
     __syncthreads();
     const int i = threadIdx.x;
     const int k = i % EX, j = (i / EX) % EY, l = i / (EX * EY);
-    if (i < NO && l < bx.ez && j < bx.ey && k < bx.ex) {
+    if (i < B::NO && l < bx.ez && j < bx.ey && k < bx.ex) {
         float acc = 0.f;
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz)
@@ -208,34 +238,57 @@ __device__ inline void band_box(const MmaJob &g, const BandBox &bx, const float 
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx)
-                    acc = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], mid[((l + dz) * MY + j + dy) * MX + k + dx], acc);
+                    acc = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], mid[((l + dz) * B::MY + j + dy) * B::MX + k + dx],
+                                         acc);
         static_cast<float *>(g.out)[((size_t)(bx.z0 + l) * g.ny + bx.y0 + j) * g.nx + bx.x0 + k] = acc;
     }
     // the next box reuses the windows
     __syncthreads();
 }
 
+// This workgroup's boxes of one kind (tiles first, first + nb, ... below
+// end, numbered within the grid), the loads of each box issued before the
+// arithmetic of the one before.
+template <int EZ, int EY, int EX>
+__device__ inline void band_kind(const MmaJob &g, const BandTiles3 &bt, int first, int end, int nb,
+                                 const float (&w)[27], float *lds) {
+    if (first >= end) return;
+    float v[8], nv[8];
+    BandBox bx = bt.box(first, g.nz, g.ny, g.nx);
+    band_load<EZ, EY, EX>(g, bx, v);
+    for (int t = first; t < end; t += nb) {
+        const BandBox cur = bx;
+        if (t + nb < end) {
+            bx = bt.box(t + nb, g.nz, g.ny, g.nx);
+            band_load<EZ, EY, EX>(g, bx, nv);
+        }
+        band_compute<EZ, EY, EX>(g, cur, v, w, lds);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = nv[r];
+    }
+}
+
 // Workgroup wg of nb computes, after its work items (its LDS free), the
-// band boxes wg, wg + nb, ... of all grids of a fused zero-halo launch.
+// band boxes wg, wg + nb, ... of all grids of a fused zero-halo launch
+// (numbered over the grids in order).
 __device__ inline void band_share3(const MmaArgs &p, int wg, int nb, float *lds) {
     if (p.edge_steps < 2) return;
     float w[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) w[i] = p.edge_w32[i];
-    int total = 0;
-    for (int j = 0; j < p.njobs; ++j) total += BandTiles3(p.job[j].nz, p.job[j].ny, p.job[j].nx).count();
-    for (int t = wg; t < total; t += nb) {
-        int j = 0, l = t;
-        for (; j < p.njobs - 1; ++j) {
-            const int c = BandTiles3(p.job[j].nz, p.job[j].ny, p.job[j].nx).count();
-            if (l < c) break;
-            l -= c;
-        }
+    int base = 0;
+    for (int j = 0; j < p.njobs; ++j) {
         const MmaJob &g = p.job[j];
-        const BandBox bx = BandTiles3(g.nz, g.ny, g.nx).box(l, g.nz, g.ny, g.nx);
-        if (bx.kind == 0) band_box<1, kBandT, kBandW>(g, bx, w, lds);
-        else if (bx.kind == 1) band_box<kBandT, 1, kBandW>(g, bx, w, lds);
-        else band_box<kBandT, kBandW, 1>(g, bx, w, lds);
+        const BandTiles3 bt(g.nz, g.ny, g.nx);
+        // this workgroup's first box of the grid, then the kinds' ranges
+        const int first = base <= wg ? wg - base : (nb - (base - wg) % nb) % nb;
+        const int e0 = bt.fz * bt.tz, e1 = e0 + bt.fy * bt.ty, e2 = bt.count();
+        const int f1 = first >= e0 ? first : first + (e0 - first + nb - 1) / nb * nb;
+        const int f2 = f1 >= e1 ? f1 : f1 + (e1 - f1 + nb - 1) / nb * nb;
+        band_kind<1, kBandT, kBandW>(g, bt, first, e0, nb, w, lds);
+        band_kind<kBandT, 1, kBandW>(g, bt, f1, e1, nb, w, lds);
+        band_kind<kBandT, kBandW, 1>(g, bt, f2, e2, nb, w, lds);
+        base += e2;
     }
 }
 
