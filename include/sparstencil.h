@@ -40,7 +40,11 @@ typedef enum {
     SS_E_BUSY = -6           /* resource in use (e.g. job table full)        */
 } ss_status;
 
-typedef enum { SS_SHAPE_BOX = 0, SS_SHAPE_STAR = 1 } ss_shape;
+/* Stencil shapes (paper Section 2.2: star and box patterns; the evaluation
+ * of Section 4 spans kernels of other patterns too).  SS_SHAPE_CUSTOM: any
+ * set of points in the (2r+1)^d box, given by the nonzero coefficients of
+ * the box (sparstencil_plan) or as a list of offsets (sparstencil_plan_points). */
+typedef enum { SS_SHAPE_BOX = 0, SS_SHAPE_STAR = 1, SS_SHAPE_CUSTOM = 2 } ss_shape;
 
 /* State storage and arithmetic of a plan. */
 typedef enum {
@@ -78,10 +82,11 @@ typedef struct {
     int32_t fuse_steps;    /* S >= 1 sweeps composed into one (at most 8):
                               periodic grids; with a zero halo, FP32-state
                               (split) grids only: 2-D with S = 2, or S = 3 at
-                              radius 1; 1-D with r*S <= 8.  The points
-                              within r(S-1) of an edge are then recomputed
-                              exactly: by a second launch (2-D), or by one
-                              more workgroup of the sweep's launch (1-D)      */
+                              radius 1; 3-D with S = 2 at radius 1; 1-D with
+                              r*S <= 8.  The points within r(S-1) of an edge
+                              are then recomputed exactly, in the sweep's
+                              launch (a second launch on the 2-D direct
+                              engine and for 2-D radii above 1)               */
     int32_t r1, r2;        /* tile width (x) and height (y); 0,0 = explore       */
     int32_t engine;        /* ss_engine                                          */
     uint32_t flags;        /* SS_FLAG_* bits, 0 by default                       */
@@ -98,8 +103,9 @@ typedef struct ss_plan_ *ss_plan_t;
  * conversion by Algorithm 1, layout exploration, metadata and lookup tables)
  * and upload its tables to the current device.
  *
- *   shape      SS_SHAPE_BOX or SS_SHAPE_STAR; a star's coefficients must be 0
- *              off the axes
+ *   shape      SS_SHAPE_BOX, SS_SHAPE_STAR (coefficients 0 off the axes) or
+ *              SS_SHAPE_CUSTOM (any pattern; planned as the box, the
+ *              matrix-core K orders keeping only the columns it uses)
  *   radius     r >= 1
  *   coeffs     host, (2r+1)^ndim FP64 values, row-major, slowest dim first
  *   ndim       1, 2 or 3
@@ -120,6 +126,25 @@ typedef struct ss_plan_ *ss_plan_t;
 ss_status sparstencil_plan(ss_plan_t *out, int32_t shape, int32_t radius, const double *coeffs,
                            int32_t ndim, const int64_t *grid_dims, int32_t dtype,
                            const ss_plan_opts *opts);
+
+/*
+ * Build a plan from a list of stencil points (SS_SHAPE_CUSTOM): point i has
+ * offset offsets[i*ndim + d] along dimension d (slowest first) and
+ * coefficient coeffs[i]; a sweep is out[p] = sum_i coeffs[i] * in~[p + o_i].
+ * The plan is the one sparstencil_plan(SS_SHAPE_CUSTOM, r, W, ...) builds,
+ * with r the largest |offset| component (1 for the centre alone) and W the
+ * (2r+1)^ndim box holding coeffs[i] at offset o_i and 0 elsewhere.
+ *   ndim       1, 2 or 3
+ *   npoints    >= 1
+ *   offsets    host, npoints * ndim int32 values; no offset twice, every
+ *              component within [-16, 16]
+ *   coeffs     host, npoints FP64 values
+ * Other arguments, ownership and errors as for sparstencil_plan; a repeated
+ * offset or one beyond radius 16 is SS_E_INVALID.
+ */
+ss_status sparstencil_plan_points(ss_plan_t *out, int32_t ndim, int32_t npoints, const int32_t *offsets,
+                                  const double *coeffs, const int64_t *grid_dims, int32_t dtype,
+                                  const ss_plan_opts *opts);
 
 /* Plan read-back (for tests and tools).  Size protocol: with buf == NULL,
  * *nbytes receives the size; otherwise *nbytes must be >= the size and the

@@ -57,6 +57,27 @@ def bounding_box(shape: str, radius: int, ndim: int, coeffs) -> np.ndarray:
     return w.copy()
 
 
+def points_box(offsets, coeffs) -> np.ndarray:
+    """Dense box of a stencil given as points (Section 2.2: a pattern of
+    neighbours, each with its weight): radius r = the largest |offset
+    component| (at least 1), coefficient i at box index offset_i + r, zero
+    elsewhere.  A repeated offset is an error."""
+    off = np.asarray(offsets, dtype=np.int64)
+    c = np.asarray(coeffs, dtype=np.float64).reshape(-1)
+    if off.ndim != 2 or off.shape[0] != c.size or off.shape[0] < 1:
+        raise ValueError("offsets (npoints, ndim) and one coefficient per point")
+    r = max(1, int(np.abs(off).max()))
+    w = np.zeros((2 * r + 1,) * off.shape[1])
+    seen = set()
+    for o, v in zip(off, c):
+        key = tuple(int(t) + r for t in o)
+        if key in seen:
+            raise ValueError("repeated offset")
+        seen.add(key)
+        w[key] = v
+    return w
+
+
 def compose(w: np.ndarray, steps: int) -> np.ndarray:
     """S-fold composition of a correlation stencil with itself.
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -653,7 +654,7 @@ void free_plan(ss_plan_ *p) {
 ss_status make_plan(ss_plan_ **out, int shape, int radius, const double *coeffs, int ndim,
                     const int64_t *grid_dims, int dtype, const ss_plan_opts *opts, bool allow_fuse) {
     if (!out || !coeffs || !grid_dims) return SS_E_INVALID;
-    if (shape != SS_SHAPE_BOX && shape != SS_SHAPE_STAR) return SS_E_INVALID;
+    if (shape != SS_SHAPE_BOX && shape != SS_SHAPE_STAR && shape != SS_SHAPE_CUSTOM) return SS_E_INVALID;
     if (ndim < 1 || ndim > 3 || radius < 1 || radius > 16) return SS_E_INVALID;
     if (state_bytes(dtype) == 0) return SS_E_INVALID;
     ss_plan_opts o{sizeof(ss_plan_opts), SS_BC_ZERO, 1, 0, 0, SS_ENGINE_AUTO, 0};
@@ -907,6 +908,35 @@ ss_status sparstencil_plan(ss_plan_t *out, int32_t shape, int32_t radius, const 
     if (out) *out = nullptr;
     try {
         return make_plan(out, shape, radius, coeffs, ndim, grid_dims, dtype, opts, true);
+    } catch (...) {
+        return SS_E_NOMEM;
+    }
+}
+
+ss_status sparstencil_plan_points(ss_plan_t *out, int32_t ndim, int32_t npoints, const int32_t *offsets,
+                                  const double *coeffs, const int64_t *grid_dims, int32_t dtype,
+                                  const ss_plan_opts *opts) {
+    if (out) *out = nullptr;
+    if (!out || !offsets || !coeffs || !grid_dims || ndim < 1 || ndim > 3 || npoints < 1) return SS_E_INVALID;
+    try {
+        int r = 1;
+        for (int64_t i = 0; i < (int64_t)npoints * ndim; ++i) {
+            if (offsets[i] < -16 || offsets[i] > 16) return SS_E_INVALID;
+            r = std::max(r, std::abs(offsets[i]));
+        }
+        const int k = 2 * r + 1;
+        size_t n = 1;
+        for (int d = 0; d < ndim; ++d) n *= (size_t)k;
+        std::vector<double> w(n, 0.0);
+        std::vector<char> seen(n, 0);
+        for (int i = 0; i < npoints; ++i) {
+            size_t at = 0;
+            for (int d = 0; d < ndim; ++d) at = at * k + (size_t)(offsets[(size_t)i * ndim + d] + r);
+            if (seen[at]) return SS_E_INVALID;
+            seen[at] = 1;
+            w[at] = coeffs[i];
+        }
+        return make_plan(out, SS_SHAPE_CUSTOM, r, w.data(), ndim, grid_dims, dtype, opts, true);
     } catch (...) {
         return SS_E_NOMEM;
     }

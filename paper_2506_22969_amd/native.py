@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsparstencil.so")
 
 SS_OK, SS_PENDING = 0, 1
 SS_E_INVALID, SS_E_UNSUPPORTED, SS_E_NOMEM, SS_E_DEVICE, SS_E_NOT_FOUND, SS_E_BUSY = -1, -2, -3, -4, -5, -6
-SHAPES = {"box": 0, "star": 1}
+SHAPES = {"box": 0, "star": 1, "custom": 2}
 DTYPES = {"f64": 0, "f32": 1, "f16": 2, "f32_split_f16": 3, "f32_split_bf16": 4, "split_bf16": 5,
           "split3_bf16": 6}
 BOUNDARIES = {"zero": 0, "periodic": 1}
@@ -27,7 +27,7 @@ ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
 (Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM,
  Q_MID) = range(12)
 
-EXPORTS = ["sparstencil_plan", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
+EXPORTS = ["sparstencil_plan", "sparstencil_plan_points", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
            "sparstencil_sweep", "sparstencil_sweep_batch", "sparstencil_launch_count", "sparstencil_grid_bytes",
            "sparstencil_status_string", "sparstencil_server_create", "sparstencil_submit",
            "sparstencil_poll", "sparstencil_job_release", "sparstencil_server_drain",
@@ -95,6 +95,10 @@ def lib():
         L.sparstencil_plan.restype = i32
         L.sparstencil_plan.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(ctypes.c_double), i32,
                                        ctypes.POINTER(i64), i32, ctypes.POINTER(PlanOpts)]
+        L.sparstencil_plan_points.restype = i32
+        L.sparstencil_plan_points.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(i32),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32,
+                                              ctypes.POINTER(PlanOpts)]
         L.sparstencil_plan_query.restype = i32
         L.sparstencil_plan_query.argtypes = [vp, i32, vp, ctypes.POINTER(sz)]
         L.sparstencil_plan_destroy.restype = i32
@@ -165,6 +169,26 @@ def sparstencil_plan(shape, radius, coeffs, ndim, grid_dims, dtype, opts=None) -
                                 w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(ndim), dims,
                                 int(dtype), popts)
     _check(st, "sparstencil_plan")
+    return int(h.value)
+
+
+def sparstencil_plan_points(offsets, coeffs, grid_dims, dtype, opts=None) -> int:
+    """Plan from a list of points: offsets (npoints, ndim) ints, coeffs
+    (npoints,) values.  Returns the plan handle (int)."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+    if off.ndim != 2:
+        raise ValueError("offsets must be (npoints, ndim)")
+    dtype = DTYPES.get(dtype, dtype)
+    w = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64).reshape(-1))
+    if w.size != off.shape[0]:
+        raise ValueError("one coefficient per offset")
+    dims = (ctypes.c_int64 * len(grid_dims))(*[int(d) for d in grid_dims])
+    h = ctypes.c_void_p()
+    popts = ctypes.byref(opts) if opts is not None else None
+    st = lib().sparstencil_plan_points(ctypes.byref(h), int(off.shape[1]), int(off.shape[0]),
+                                       off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), dims, int(dtype), popts)
+    _check(st, "sparstencil_plan_points")
     return int(h.value)
 
 
@@ -269,17 +293,21 @@ def make_opts(boundary="zero", fuse_steps=1, r1=0, r2=0, engine="auto", flags=0)
 
 
 class Plan:
-    """Owns one plan handle; see sparstencil_plan for the arguments."""
+    """Owns one plan handle; see sparstencil_plan for the arguments (shape
+    "custom" with offsets=(npoints, ndim) and one coefficient per point:
+    sparstencil_plan_points; radius is then unused)."""
 
     def __init__(self, shape, radius, coeffs, grid_dims, dtype, boundary="zero", fuse_steps=1,
-                 r1=0, r2=0, engine="auto", host_only=False):
+                 r1=0, r2=0, engine="auto", host_only=False, offsets=None):
         grid_dims = tuple(int(d) for d in grid_dims)
         self.grid_dims = grid_dims
         self.dtype = dtype
         self.handle = 0
-        self.handle = sparstencil_plan(shape, radius, coeffs, len(grid_dims), grid_dims, dtype,
-                                       make_opts(boundary, fuse_steps, r1, r2, engine,
-                                                 FLAG_HOST_ONLY if host_only else 0))
+        opts = make_opts(boundary, fuse_steps, r1, r2, engine, FLAG_HOST_ONLY if host_only else 0)
+        if offsets is not None:
+            self.handle = sparstencil_plan_points(offsets, coeffs, grid_dims, dtype, opts)
+        else:
+            self.handle = sparstencil_plan(shape, radius, coeffs, len(grid_dims), grid_dims, dtype, opts)
 
     def close(self):
         if getattr(self, "handle", 0):

@@ -338,3 +338,36 @@ def test_sweep_batch_exceeds_cus(engine, dtype, fuse):
         err = normwise_err(got, ref)
         tol = apriori_bound(info, w, fuse, dtype)
         assert err <= tol, (i, err, tol)
+
+
+CUSTOM_POINTS = {  # (offsets, coefficients) of patterns neither box nor star
+    2: ([(0, 0), (0, -1), (-1, 0), (-1, -1), (0, -2), (2, 1), (1, 2)],
+        [0.45, 0.2, 0.15, 0.1, 0.05, 0.03, 0.02]),
+    3: ([(0, 0, 0), (0, 0, -1), (0, -1, 0), (-1, 0, 0), (1, 1, 1), (-1, 1, 0)],
+        [0.5, 0.15, 0.15, 0.1, 0.05, 0.05]),
+    1: ([(0,), (-1,), (-3,), (2,)], [0.6, 0.25, 0.1, 0.05]),
+}
+
+
+@pytest.mark.parametrize("engine", ["smfmac", "mfma", "direct"])
+@pytest.mark.parametrize("ndim,dims", [(2, (200, 300)), (2, (129, 131)), (3, (20, 40, 264)), (1, (5000,))])
+@pytest.mark.parametrize("boundary", ["zero", "periodic"])
+def test_custom_points(engine, ndim, dims, boundary):
+    """Stencils given as point lists (sparstencil_plan_points, upwind-like
+    asymmetric patterns) against the oracle sweeping the box of the same
+    points (points_box, itself pinned against the point sum)."""
+    from oracle import tables as T
+    offs, c = CUSTOM_POINTS[ndim]
+    w = T.points_box(offs, c)
+    x0 = synthetic.grid_f32(dims, seed=21)
+    steps = 5
+    with native.Plan("custom", 0, c, dims, "f32_split_f16", boundary=boundary, engine=engine, offsets=offs) as p:
+        info = p.info
+        assert info["engine_name"] == engine
+        kk = len(p.table(native.Q_KERNEL_PERM)) if engine != "direct" else 0
+        got = run_plan(p, x0, steps)
+    ref = oracle_direct.run(x0.astype(np.float64), w, steps, periodic=(boundary == "periodic"))
+    err = normwise_err(got, ref)
+    tol = apriori_bound(info, w, steps, "f32_split_f16", kk)
+    print(f"custom {ndim}-D {engine} {dims} {boundary} err={err:.3e} tol={tol:.3e}")
+    assert err <= tol

@@ -480,3 +480,34 @@ def test_compaction_counts_fused_13_point_star_at_16x2():
     assert 74 <= len(groups) <= 80
     assert groups[:56] == [perm[j:j + 4] for j in range(0, len(perm), 4)
                            if holds(perm[j:j + 2]) and holds(perm[j + 2:j + 4])]
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_points_box_sweep_equals_point_sum(ndim):
+    """A stencil given as points: the oracle's box of it, swept by the direct
+    oracle, equals sum_i c_i x~[p + o_i] written out point by point on a
+    tiny zero-halo grid (brute force, no box involved)."""
+    from oracle import direct
+    rng = np.random.default_rng(7 + ndim)
+    offs = {tuple(int(v) for v in rng.integers(-2, 3, ndim)) for _ in range(6)} | {(0,) * ndim, (2,) + (0,) * (ndim - 1)}
+    offs = sorted(offs)
+    c = rng.uniform(-1, 1, len(offs))
+    w = T.points_box(offs, c)
+    assert w.shape == (5,) * ndim and np.count_nonzero(w) == len(offs)
+    shape = {1: (11,), 2: (6, 7), 3: (4, 5, 6)}[ndim]
+    x = rng.uniform(0, 1, shape)
+    want = np.zeros(shape)
+    for p in np.ndindex(*shape):
+        for o, ci in zip(offs, c):
+            q = tuple(a + b for a, b in zip(p, o))
+            if all(0 <= qi < n for qi, n in zip(q, shape)):
+                want[p] += ci * x[q]
+    got = direct.run(x, w, 1)
+    assert np.allclose(got, want, rtol=0, atol=1e-14)
+
+
+def test_points_box_rejects_repeats_and_sizes_radius():
+    assert T.points_box([(0, 0)], [2.0]).shape == (3, 3)
+    assert T.points_box([(0, 3)], [1.0]).shape == (7, 7)
+    with pytest.raises(ValueError):
+        T.points_box([(0, 1), (0, 1)], [1.0, 2.0])

@@ -397,3 +397,31 @@ def test_three_part_planes_scope():
         dims = kw.pop("dims", (64, 64))
         with pytest.raises(native.SparStencilError):
             native.Plan("box", 1, w, dims, "split3_bf16", host_only=True, **kw)
+
+
+def test_custom_points_plan_equals_box_plan():
+    """sparstencil_plan_points builds the plan of the box holding the
+    points' coefficients (the oracle's points_box), shape SS_SHAPE_CUSTOM:
+    same coefficients, same kernel K order; a radius-2 point list gives a
+    5-wide box; repeated offsets, offsets beyond 16 and mismatched lengths
+    are rejected."""
+    offs = [(0, 0), (0, -1), (-1, 0), (-1, -1), (0, -2), (2, 1)]
+    c = [0.5, 0.2, 0.15, 0.1, 0.04, 0.01]
+    w = T.points_box(offs, c)
+    dims = (256, 256)
+    with native.Plan("custom", 0, c, dims, "f32_split_f16", offsets=offs, host_only=True) as p:
+        info = p.info
+        wk = p.table(native.Q_COEFFS)
+        perm = p.table(native.Q_KERNEL_PERM)
+    with native.Plan("custom", 2, w, dims, "f32_split_f16", host_only=True) as q:
+        assert np.array_equal(q.table(native.Q_KERNEL_PERM), perm)
+    assert info["k"] == 5 and np.array_equal(wk.reshape(5, 5), w)
+    # fewer used columns than the box: the K order drops the rest
+    with native.Plan("box", 2, np.ones((5, 5)), dims, "f32_split_f16", host_only=True) as b:
+        assert len(perm) <= len(b.table(native.Q_KERNEL_PERM))
+    for bad_offs, bad_c in [([(0, 1), (0, 1)], [1.0, 2.0]), ([(0, 17)], [1.0]), ([(0, 1)], [1.0, 2.0])]:
+        with pytest.raises((native.SparStencilError, ValueError)):
+            native.Plan("custom", 0, bad_c, dims, "f32_split_f16", offsets=bad_offs, host_only=True)
+    # a custom box pattern is not held to the star rule
+    with native.Plan("custom", 1, np.arange(9.0).reshape(3, 3), dims, "f32_split_f16", host_only=True) as p:
+        assert p.info["k"] == 3
