@@ -163,12 +163,26 @@ enum {
     SS_Q_MODEL = 8,       /* double[n][7]: r1, r2, T, T_compute, T_global,
                              T_shared, K_pad for every candidate layout          */
     SS_Q_KERNEL_LUT = 9,  /* int32[n]: LDS offsets the launched kernel gathers   */
-    SS_Q_KERNEL_PERM = 10 /* int32[n]: A' column per K slot of the launched
+    SS_Q_KERNEL_PERM = 10, /* int32[n]: A' column per K slot of the launched
                              matrix-core kernel, -1 = zero column: SS_Q_PERM's
                              groups with the columns the stencil never uses
                              dropped and re-paired (sparse), or the used column
                              pairs in natural order (dense); empty for the
                              direct engine                                        */
+    SS_Q_KERNEL_FRAGS = 12 /* bytes: the launched matrix-core kernel's A
+                             operand registers.  int32 {MB, KC, mode (0 sparse,
+                             1 dense), parts (2, or 3 for SS_SPLIT3_BF16)},
+                             then uint16 hi[MB][KC][64][8], lo[...] (and
+                             mid[...] with 3 parts): lane l's eight 16-bit
+                             values of M block MB, K chunk KC; sparse: then
+                             uint32 idx[MB][KC][64], the 2-bit position of
+                             value e within its 4-group at bits 2e+1:2e.
+                             Sparse lane l holds row l % 16 and, for value e,
+                             4-group 4*(2*((l/16)%2) + e/4) + 2*(l/32) +
+                             (e/2)%2 of the chunk (K slots 4g .. 4g+3), two
+                             values (e even, e odd) per group; dense lane l
+                             holds row l % 16, K slots 8*(l/16) .. +7.  Empty
+                             for the direct engine                           */
 };
 
 typedef struct {

@@ -23,6 +23,7 @@ struct ss_plan_ {
     std::vector<double> model;        // rows of 7
     std::vector<int32_t> kernel_lut;
     std::vector<int32_t> kperm;       // A' column per K slot of the launched kernel
+    std::vector<uint8_t> kernel_frags; // SS_Q_KERNEL_FRAGS: the kernel's A fragments
     // device
     void *dev = nullptr;
     ss::MmaArgs margs{};

@@ -169,6 +169,15 @@ ss_status build_mma_tables(ss_plan_ *p, const Geometry &gm, const std::vector<in
     std::memcpy(blob->data() + *off_idx, aidx.data(), aidx.size() * 4);
     std::memcpy(blob->data() + *off_boff, boff.data(), boff.size() * 4);
     p->kernel_lut = boff;
+    // read-back copy of the A fragments (SS_Q_KERNEL_FRAGS)
+    const int32_t head[4] = {MB, kc_count, mode, three ? 3 : 2};
+    std::vector<uint8_t> &fr = p->kernel_frags;
+    fr.assign((const uint8_t *)head, (const uint8_t *)head + sizeof head);
+    auto put = [&](const void *d, size_t n) { fr.insert(fr.end(), (const uint8_t *)d, (const uint8_t *)d + n); };
+    put(ahi.data(), ahi.size() * 2);
+    put(alo.data(), alo.size() * 2);
+    if (three) put(amid.data(), amid.size() * 2);
+    if (mode == kSparse) put(aidx.data(), aidx.size() * 4);
     return SS_OK;
 }
 
@@ -1023,6 +1032,7 @@ ss_status sparstencil_plan_query(ss_plan_t p, int32_t what, void *buf, size_t *n
         case SS_Q_MODEL: return copy_out(p->model, buf, nbytes);
         case SS_Q_KERNEL_LUT: return copy_out(p->kernel_lut, buf, nbytes);
         case SS_Q_KERNEL_PERM: return copy_out(p->kperm, buf, nbytes);
+        case SS_Q_KERNEL_FRAGS: return copy_out(p->kernel_frags, buf, nbytes);
         default: return SS_E_INVALID;
     }
 }

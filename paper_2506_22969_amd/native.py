@@ -25,7 +25,7 @@ BOUNDARIES = {"zero": 0, "periodic": 1}
 ENGINES = {"auto": 0, "smfmac": 1, "mfma": 2, "direct": 3}
 ENGINE_NAMES = {v: k for k, v in ENGINES.items()}
 (Q_INFO, Q_COEFFS, Q_PERM, Q_VALUES, Q_META, Q_HI, Q_LO, Q_LUT, Q_MODEL, Q_KERNEL_LUT, Q_KERNEL_PERM,
- Q_MID) = range(12)
+ Q_MID, Q_KERNEL_FRAGS) = range(13)
 
 EXPORTS = ["sparstencil_plan", "sparstencil_plan_points", "sparstencil_plan_query", "sparstencil_plan_destroy", "sparstencil_run",
            "sparstencil_sweep", "sparstencil_sweep_batch", "sparstencil_launch_count", "sparstencil_grid_bytes",
@@ -337,6 +337,24 @@ class Plan:
               Q_HI: np.uint16, Q_LO: np.uint16, Q_LUT: np.int32, Q_MODEL: np.float64,
               Q_KERNEL_LUT: np.int32, Q_KERNEL_PERM: np.int32, Q_MID: np.uint16}[what]
         return np.frombuffer(raw, dtype=dt).copy()
+
+    def kernel_fragments(self) -> dict:
+        """The matrix-core kernel's A operand registers (SS_Q_KERNEL_FRAGS):
+        hi, lo (and mid) as uint16 [MB][KC][64][8], idx as uint32
+        [MB][KC][64] (sparse), with mode and parts."""
+        raw = sparstencil_plan_query(self.handle, Q_KERNEL_FRAGS)
+        if not raw:
+            return {}
+        mb, kc, mode, parts = np.frombuffer(raw[:16], dtype=np.int32)
+        n = int(mb) * int(kc) * 64 * 8
+        at = 16
+        out = {"mode": "sparse" if mode == 0 else "dense", "parts": int(parts)}
+        for name in ("hi", "lo", "mid")[:int(parts)]:
+            out[name] = np.frombuffer(raw[at:at + 2 * n], dtype=np.uint16).reshape(mb, kc, 64, 8).copy()
+            at += 2 * n
+        if mode == 0:
+            out["idx"] = np.frombuffer(raw[at:at + 4 * n // 8], dtype=np.uint32).reshape(mb, kc, 64).copy()
+        return out
 
     def run(self, inp, out, steps, stream=None):
         sparstencil_run(self.handle, inp, out, steps, stream)
