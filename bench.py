@@ -57,7 +57,7 @@ def parse():
                     help="skip the measured sweep over the instantiated tiles")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (Heat-2D FP64, radius-3 bfloat16 planes, 3-D)")
-    ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p", "heat1d3p", "1d5p"],
+    ap.add_argument("--profile", choices=["box2d9p", "box2d49p_planes", "box3d27p", "heat3d7p", "heat1d3p", "1d5p"],
                     help="only copy the grid once and run four sweeps of one workload on the sparse engine (for profilers)")
     return ap.parse_args()
 
@@ -575,9 +575,10 @@ def profile_only(name: str, fuse: int):
         x = torch.from_numpy(synthetic.grid_f32((10_240_000,), seed=0)).to("cuda:0")
         plan = native.Plan("box", radius, w, (10_240_000,), "f32_split_f16", engine="smfmac")
     else:
-        w = synthetic.random_coeffs("box", 1, 3, seed=70)[0]
+        shape, seed = ("box", 70) if name == "box3d27p" else ("star", 29)
+        w = synthetic.random_coeffs(shape, 1, 3, seed=seed)[0]
         x = torch.from_numpy(synthetic.grid_f32((512, 512, 512), seed=0)).to("cuda:0")
-        plan = native.Plan("box", 1, w, (512, 512, 512), "f32_split_f16", engine="smfmac", fuse_steps=min(fuse, 2))
+        plan = native.Plan(shape, 1, w, (512, 512, 512), "f32_split_f16", engine="smfmac", fuse_steps=min(fuse, 2))
     y = torch.empty_like(x)
     # one device copy of the grid: a plain copy kernel of known size, which
     # calibrates the HBM byte counters

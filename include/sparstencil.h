@@ -212,7 +212,11 @@ ss_status sparstencil_plan_destroy(ss_plan_t plan);
  *            they must not overlap.  `in` serves as the second mesh of the
  *            ping-pong, so its contents are unspecified afterwards.
  *   steps    >= 0; 0 copies in to out.  With fuse_steps S > 1, floor(steps/S)
- *            fused launches run, then steps mod S unfused ones.
+ *            fused launches run, then steps mod S unfused ones.  A 2-D
+ *            FP64 grid of at most 2^20 points on the direct engine runs up
+ *            to 16/r sweeps per launch (temporal blocking in LDS; each
+ *            point's arithmetic as in single sweeps), so a run of at most
+ *            16/r sweeps is one launch.
  * Errors: SS_E_INVALID (null, in == out, steps < 0), SS_E_DEVICE (launch).
  */
 ss_status sparstencil_run(ss_plan_t plan, void *in, void *out, int64_t steps, void *stream);
@@ -236,8 +240,8 @@ ss_status sparstencil_sweep(ss_plan_t plan, const void *in, void *out, void *str
 ss_status sparstencil_sweep_batch(ss_plan_t plan, int32_t n, const void *const *in, void *const *out,
                                   void *stream);
 
-/* Number of sweep kernels `run` launches for `steps` sweeps (0 for a copy);
- * an even count is preceded by one device-to-device copy of the grid. */
+/* Number of kernels `run` launches for `steps` sweeps (0 for a copy); an
+ * even count is preceded by one device-to-device copy of the grid. */
 int64_t sparstencil_launch_count(ss_plan_t plan, int64_t steps);
 
 /* Bytes of one grid buffer of the plan (all planes). */

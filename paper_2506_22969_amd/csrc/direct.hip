@@ -264,6 +264,82 @@ hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Several sweeps of a small 2-D FP64 grid in one launch (temporal
+// blocking): each workgroup owns a kTbTile x kTbTile output tile, loads the
+// inputs within H = S*r of it into LDS (zero outside a zero-halo grid,
+// wrapped on a periodic one), applies the S sweeps there -- sweep s on the
+// window shrunk by s*r from each side, the part the later sweeps still read,
+// with points outside a zero-halo grid held at zero -- and stores its tile.
+// Each point's sum runs in k_direct's order (rows, then columns, fused
+// multiply-adds; the zeros of a zero halo add nothing), so the result is
+// bit for bit that of S single-sweep launches.
+constexpr int kTbTile = 32, kTbWin = kTbTile + 2 * kTbHalo;
+
+template <int RAD>
+__global__ __launch_bounds__(256) void k_tb2d(DirectArgs a) {
+    __shared__ double buf[2][kTbWin * kTbWin];
+    const DirectJob &g = a.job[0];
+    const int S = a.steps, H = S * RAD, W = kTbTile + 2 * H;
+    const int ntx = (g.nx + kTbTile - 1) / kTbTile;
+    const int y0 = (int)(blockIdx.x / ntx) * kTbTile - H, x0 = (int)(blockIdx.x % ntx) * kTbTile - H;
+    const double *in = static_cast<const double *>(g.in);
+    const double *w = static_cast<const double *>(a.w);
+    for (int i = threadIdx.x; i < W * W; i += 256) {
+        int gy = y0 + i / W, gx = x0 + i % W;
+        double v = 0.0;
+        if (a.periodic) {
+            gy = wrap_i(gy, g.ny);
+            gx = wrap_i(gx, g.nx);
+            v = in[(size_t)gy * g.nx + gx];
+        } else if (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx) {
+            v = in[(size_t)gy * g.nx + gx];
+        }
+        buf[0][i] = v;
+    }
+    __syncthreads();
+    for (int st = 1; st <= S; ++st) {
+        const double *src = buf[(st - 1) & 1];
+        double *dst = buf[st & 1];
+        const int lo = st * RAD, n = W - 2 * lo;
+        for (int i = threadIdx.x; i < n * n; i += 256) {
+            const int wy = lo + i / n, wx = lo + i % n;
+            const int gy = y0 + wy, gx = x0 + wx;
+            double acc = 0.0;
+            if (a.periodic || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx)) {
+#pragma unroll
+                for (int dy = 0; dy < 2 * RAD + 1; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2 * RAD + 1; ++dx)
+                        acc = __builtin_fma(w[dy * (2 * RAD + 1) + dx], src[(wy - RAD + dy) * W + wx - RAD + dx], acc);
+            }
+            dst[wy * W + wx] = acc;
+        }
+        __syncthreads();
+    }
+    const double *res = buf[S & 1];
+    double *out = static_cast<double *>(g.out);
+    for (int i = threadIdx.x; i < kTbTile * kTbTile; i += 256) {
+        const int wy = H + i / kTbTile, wx = H + i % kTbTile;
+        const int gy = y0 + wy, gx = x0 + wx;
+        if (gy < g.ny && gx < g.nx) out[(size_t)gy * g.nx + gx] = res[wy * W + wx];
+    }
+}
+
+hipError_t launch_direct_tb(DirectArgs &a, hipStream_t s) {
+    if (a.njobs != 1 || a.steps < 1 || a.steps * a.rx > kTbHalo || a.rx != a.ry || a.rz != 0)
+        return hipErrorInvalidValue;
+    const DirectJob &g = a.job[0];
+    const int blocks = ((g.nx + kTbTile - 1) / kTbTile) * ((g.ny + kTbTile - 1) / kTbTile);
+    switch (a.rx) {
+        case 1: hipLaunchKernelGGL(k_tb2d<1>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_tb2d<2>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_tb2d<3>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(k_tb2d<4>, dim3(blocks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s) {
     if (a.njobs < 1 || a.njobs > kMaxJobs) return hipErrorInvalidValue;
     switch (kind) {

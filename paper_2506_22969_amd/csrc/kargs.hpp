@@ -82,6 +82,7 @@ struct DirectArgs {
     int rz, ry, rx;
     int periodic;
     const void *w;           // coefficients (FP64 for an FP64 state, else FP32)
+    int steps;               // sweeps per launch of the temporal-block kernel
 };
 
 // Key of an instantiated 2-D MMA kernel.
@@ -132,5 +133,10 @@ int mma2d_f64_pitch(int rad);
 
 // Fills total_blocks and the jobs' block0 from their grid sizes.
 hipError_t launch_direct(DirectArgs &a, int kind, hipStream_t s);
+
+// Several sweeps of one small 2-D FP64 grid in one launch (temporal
+// blocking, a.steps sweeps with a.steps * radius <= kTbHalo, radius <= 4).
+constexpr int kTbHalo = 16;
+hipError_t launch_direct_tb(DirectArgs &a, hipStream_t s);
 
 }  // namespace ss

@@ -33,6 +33,9 @@ struct ss_plan_ {
     bool host_only = false;
     uint64_t klass = 0;               // equal for plans with identical device tables
     ss_plan_ *rem = nullptr;          // unfused plan for leftover sweeps
+    // small 2-D FP64 grids on the direct engine: run() applies up to tb
+    // sweeps per launch (temporal blocking); 0 = one sweep per launch
+    int tb = 0;
     // two fused sweeps on a 2-D zero-halo grid: the band within edge_rad of
     // an edge is recomputed exactly from the unfused coefficients
     std::vector<double> w1;           // unfused coefficients

@@ -649,6 +649,10 @@ ss_status plan_direct(ss_plan_ *p) {
     p->engine = SS_ENGINE_DIRECT;
     p->info.passes = 1;
     p->info.sigma = 1.0;
+    // a small 2-D FP64 grid (a sweep takes a few microseconds, about what a
+    // launch costs) runs several sweeps per launch in LDS
+    if (f64 && p->ndim == 2 && p->fuse == 1 && p->rad <= 4 && p->dims[1] * p->dims[2] <= (int64_t)1 << 20)
+        p->tb = kTbHalo / p->rad;
     return SS_OK;
 }
 
@@ -963,6 +967,7 @@ size_t sparstencil_grid_bytes(ss_plan_t p) {
 
 int64_t sparstencil_launch_count(ss_plan_t p, int64_t steps) {
     if (!p || steps <= 0) return 0;
+    if (p->tb) return (steps + p->tb - 1) / p->tb;
     return steps / p->fuse + steps % p->fuse;
 }
 
@@ -973,9 +978,9 @@ ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void 
     if (steps == 0)
         return hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s) == hipSuccess ? SS_OK : SS_E_DEVICE;
     const int64_t fused = steps / p->fuse, rest = steps % p->fuse;
-    const int64_t total = fused + rest;
-    // Ping-pong between the two meshes so that the last sweep writes `out`;
-    // with an even number of sweeps the input is first copied into `out`.
+    const int64_t total = sparstencil_launch_count(p, steps);
+    // Ping-pong between the two meshes so that the last launch writes `out`;
+    // with an even number of launches the input is first copied into `out`.
     void *src = in, *dst = out;
     if (total % 2 == 0) {
         if (hipMemcpyAsync(out, in, bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return SS_E_DEVICE;
@@ -983,8 +988,17 @@ ss_status sparstencil_run(ss_plan_t p, void *in, void *out, int64_t steps, void 
         dst = in;
     }
     for (int64_t i = 0; i < total; ++i) {
-        const ss_plan_ *q = i < fused ? p : p->rem;
-        if (ss::sweep_one(q, src, dst, s) != hipSuccess) return SS_E_DEVICE;
+        if (p->tb) {
+            // the steps shared out evenly over the launches
+            ss::DirectArgs a = p->dargs;
+            a.njobs = 1;
+            a.job[0] = ss::DirectJob{src, dst, 1, (int)p->dims[1], (int)p->dims[2], 0};
+            a.steps = (int)(steps / total + (i < steps % total ? 1 : 0));
+            if (ss::launch_direct_tb(a, s) != hipSuccess) return SS_E_DEVICE;
+        } else {
+            const ss_plan_ *q = i < fused ? p : p->rem;
+            if (ss::sweep_one(q, src, dst, s) != hipSuccess) return SS_E_DEVICE;
+        }
         std::swap(src, dst);
     }
     return SS_OK;

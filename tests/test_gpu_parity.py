@@ -96,12 +96,42 @@ def test_bf16_split_and_tiles(engine, r1, r2):
 
 
 def test_star5_heat2d_f64_direct_c1():
-    # Heat-2D Jacobi, 256x256 FP64, zero halo, 10 sweeps.
+    # Heat-2D Jacobi, 256x256 FP64, zero halo, 10 sweeps: one launch (ten
+    # sweeps in LDS), equal to the oracle (every product is exact)
     w = synthetic.heat2d_coeffs()
     x0 = synthetic.grid_f64((256, 256), seed=0)
     with native.Plan("star", 1, w, (256, 256), "f64") as p:
+        assert p.info["engine_name"] == "direct" and p.launch_count(10) == 1
         got = run_plan(p, x0, 10)
     ref = oracle_direct.run(x0, w, 10)
+    assert normwise_err(got, ref) <= 1e-13
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("radius", [1, 2, 4])
+@pytest.mark.parametrize("dims,boundary", [((256, 256), "zero"), ((129, 131), "periodic"), ((7, 5), "zero"),
+                                           ((5, 9), "periodic"), ((300, 520), "zero")])
+@pytest.mark.parametrize("steps", [1, 3, 16, 37])
+def test_f64_temporal_blocks_equal_single_sweeps(radius, dims, boundary, steps):
+    """Small FP64 grids run up to 16/r sweeps per launch in LDS: the result
+    equals, bit for bit, the same sweeps run one per launch
+    (sparstencil_sweep), and the FP64 oracle to 1e-13."""
+    w, _ = synthetic.random_coeffs("box", radius, 2, seed=2, grid_shape=dims)
+    x0 = synthetic.grid_f64(dims, seed=4)
+    if boundary == "periodic" and min(dims) < radius:
+        pytest.skip("periodic grid narrower than the stencil")
+    with native.Plan("box", radius, w, dims, "f64", boundary=boundary, engine="direct") as p:
+        assert p.launch_count(steps) == -(-steps // (16 // radius))
+        got = run_plan(p, x0, steps)
+        a = torch.from_numpy(x0).to(DEV)
+        b = torch.empty_like(a)
+        for _ in range(steps):
+            p.sweep(a, b, stream())
+            a, b = b, a
+        torch.cuda.synchronize()
+        single = a.cpu().numpy()
+    assert np.array_equal(got, single)
+    ref = oracle_direct.run(x0, w, steps, periodic=(boundary == "periodic"))
     assert normwise_err(got, ref) <= 1e-13
 
 
