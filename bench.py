@@ -4,7 +4,7 @@ binary16 hi+lo split products on gfx950 sparse MFMA (SMFMAC).
 One step = one sparstencil_run of the whole workload (100 sweeps) on grids
 already resident in HBM; by default three sweeps are fused per launch (the
 composed stencil, with the band within 2r of the edges recomputed exactly by
-a second, small launch), as the paper fuses three sweeps.  Prints one JSON line
+the same launch), as the paper fuses three sweeps.  Prints one JSON line
 with GStencil/s (paper Section 4.1, Eq. 12: T * prod(N_i) / (t * 1e9)),
 latency percentiles, the dense-MFMA and direct-FMA engines on the same
 workload (fused and unfused), the roofline of the sparse sweep launch (HIP
@@ -651,7 +651,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(args.fuse),
             "kernel": "k_mma2c (sparse, binary16 split)" +
-                      (f", {args.fuse} sweeps per launch, plus the edge-band launch" if args.fuse > 1 else ""),
+                      (f", {args.fuse} sweeps per launch, the edge band computed in the launch" if args.fuse > 1 else ""),
             "sweep_ms": round(sweep_ms, 4), "algorithmic_bytes_per_launch": alg_bytes,
             "frac_of_measured_hbm": round(achieved / peaks["hbm_copy_gbs"], 4),
             "smfmac": {"issued_dense_equiv_flops_per_launch": mma_flops, "achieved_tflops": round(mma_tf, 1),
