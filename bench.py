@@ -70,15 +70,16 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_entry(fuse: int):
-    """Measured HBM bytes per launch, only if taken on the current kernel and
-    fusion."""
+def traffic_entry(fuse: int, tile):
+    """Measured HBM bytes per launch, only if taken on the current kernel
+    source, fusion and tile."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha256_16") != kernel_hash() or t.get("fuse_steps", 1) != fuse:
+    if (t.get("kernel_sha256_16") != kernel_hash() or t.get("fuse_steps", 1) != fuse
+            or t.get("tile") != list(tile)):
         return None
     return t.get("bytes_per_launch")
 
@@ -649,8 +650,8 @@ def main():
     mma_flops = issued_mma(info) * 2.0 * 16 * 16 * 64
     mma_tf = mma_flops / (sweep_ms / 1e3) / 1e12
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(args.fuse),
-            "kernel": "k_mma2c (sparse, binary16 split)" +
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_entry(args.fuse, (info["r1"], info["r2"])),
+            "kernel": f"k_mma2c (sparse, binary16 split, tile {info['r1']}x{info['r2']})" +
                       (f", {args.fuse} sweeps per launch, the edge band computed in the launch" if args.fuse > 1 else ""),
             "sweep_ms": round(sweep_ms, 4), "algorithmic_bytes_per_launch": alg_bytes,
             "frac_of_measured_hbm": round(achieved / peaks["hbm_copy_gbs"], 4),

@@ -595,8 +595,9 @@ def explore(k: int, ndim: int, grid, candidates, elem_bytes: int, coef_bytes: in
     """Eq. 11: argmin of T over the candidate set.
 
     Reading of the tie-break (the paper gives none): smallest T (relative
-    tolerance 1e-12); then smallest on-chip time max(T_compute, T_shared);
-    then smaller K_pad; then smaller r1*r2; then smaller r1.  Returns
+    tolerance 1e-12); then smallest T_compute (the matrix work, which is
+    what separates layouts that tie on an HBM-bound T); then smallest
+    T_shared; then smaller K_pad; then smaller r1*r2; then smaller r1.  Returns
     ((r1, r2), table) with table[(r1, r2)] = model_time(...)."""
     table = {}
     for (r1, r2) in candidates:
@@ -614,9 +615,10 @@ def _better(ta, ca, tb, cb) -> bool:
         return abs(x - y) <= 1e-12 * max(abs(x), abs(y))
     if not close(ta[0], tb[0]):
         return ta[0] < tb[0]
-    oa, ob = max(ta[1], ta[3]), max(tb[1], tb[3])
-    if not close(oa, ob):
-        return oa < ob
+    if not close(ta[1], tb[1]):
+        return ta[1] < tb[1]
+    if not close(ta[3], tb[3]):
+        return ta[3] < tb[3]
     if ta[4] != tb[4]:
         return ta[4] < tb[4]
     if ca[0] * ca[1] != cb[0] * cb[1]:

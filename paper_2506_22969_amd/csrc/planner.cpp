@@ -455,12 +455,12 @@ ModelRow model_time(const ModelParams &mp, int r1, int r2) {
 
 static bool close_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::max(std::fabs(a), std::fabs(b)); }
 
-// Eq. 11 tie-break: T, then on-chip time max(T_compute, T_shared), then
-// K_pad, then r1*r2, then r1.
+// Eq. 11 tie-break: T, then T_compute (the matrix work separates layouts
+// that tie on an HBM-bound T), then T_shared, then K_pad, then r1*r2, then r1.
 bool model_better(const ModelRow &a, const ModelRow &b) {
     if (!close_rel(a.t, b.t)) return a.t < b.t;
-    const double oa = std::max(a.t_compute, a.t_shared), ob = std::max(b.t_compute, b.t_shared);
-    if (!close_rel(oa, ob)) return oa < ob;
+    if (!close_rel(a.t_compute, b.t_compute)) return a.t_compute < b.t_compute;
+    if (!close_rel(a.t_shared, b.t_shared)) return a.t_shared < b.t_shared;
     if (a.k_pad != b.k_pad) return a.k_pad < b.k_pad;
     if (a.r1 * a.r2 != b.r1 * b.r2) return a.r1 * a.r2 < b.r1 * b.r2;
     return a.r1 < b.r1;

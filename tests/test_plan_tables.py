@@ -170,6 +170,9 @@ def test_kernel_order_matches_oracle(shape, radius, fuse, dtype, engine):
     dims = (256, 256)
     w, _ = synthetic.random_coeffs(shape, radius, 2, seed=45 if radius == 3 else 1, grid_shape=dims)
     kw = dict(boundary="periodic", fuse_steps=fuse) if fuse > 1 else {}
+    if shape == "star" and radius == 3:
+        # a tile on which dropping the unused columns shortens K
+        kw.update(r1=8, r2=4 if engine == "smfmac" or fuse == 1 else 2)
     with native.Plan(shape, radius, w, dims, dtype, engine=engine, host_only=True, **kw) as p:
         info = p.info
         got = p.table(native.Q_KERNEL_PERM)
