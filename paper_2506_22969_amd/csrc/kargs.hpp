@@ -108,7 +108,9 @@ enum DirectKind { kDirectF32 = 0, kDirectF64 = 1, kDirectPlanes = 2 };
 // 3-D MMA kernels (FP32 state), same conventions; the launch also fills the
 // jobs' z-chunk depth zc.
 MmaLaunch find_mma3d(const MmaKey &key);
-bool mma3d_geometry(const MmaKey &key, int *wgh, int *row);
+// Rows of a work item and the converted plane's row pitch (dwords), dwords
+// per pair and pairs between row gaps.
+bool mma3d_geometry(const MmaKey &key, int *wgh, int *row, int *pw, int *padg);
 int mma3d_keys(int rad, int mode, int part, MmaKey *out, int max);
 
 // Direct 2-D sweep from the same LDS-DMA slab pipeline (FP32 state or

@@ -166,4 +166,42 @@ struct Mma3Geom {
     static_assert(NP >= 2 * RAD + 2, "ring too small for the stencil depth");
 };
 
+// Converted plane of the 3-D matrix kernels: the pairs of a staged FP32
+// plane from column P0 = HL - RAD on (the first column any tile reads), each
+// as its packed hi word and packed lo word (PW = 2 dwords), pair j of a row
+// at dword pos(j) = PW * (j + j / PADG) and rows ROWC dwords apart -- the
+// 2-D kernels' converted layout, which starts the 16 tiles of a unit in 16
+// different bank pairs.  The ring of staged planes gives up the room.
+template <int R1, int R2, int RAD>
+struct Conv3Geom {
+    using G = Mma3Geom<R1, R2, RAD>;
+    static constexpr int P0 = G::HL - RAD;
+    static constexpr int NPAIR = kBandX / 2 + RAD;
+    static constexpr int PW = 2;
+    static constexpr int PADG = R1 == 8 ? 4 : 8;
+    static constexpr int pos(int j) { return PW * (j + j / PADG); }
+    static constexpr bool banks_ok(int rowc) {
+        int seen[32] = {};
+        for (int n = 0; n < 16; ++n) {
+            const int b = ((n / G::NBX) * R2 * rowc + pos((n % G::NBX) * R1 / 2)) % 32;
+            if (b % 2 != 0 || seen[b]) return false;
+            seen[b] = 1;
+        }
+        return true;
+    }
+    static constexpr int pick_rowc() {
+        const int lo = (pos(NPAIR - 1) + PW + 1) / 2 * 2;
+        for (int r = lo; r < lo + 64; r += 2)
+            if (banks_ok(r)) return r;
+        return lo;
+    }
+    static constexpr int ROWC = pick_rowc();
+    static constexpr int CONV_BYTES = G::SROWS * ROWC * 4;
+    static constexpr int NPF = (kLdsBytes - CONV_BYTES) / G::PLANE_BYTES;
+    static constexpr int NP = NPF < 8 ? NPF : 8;                       // ring slots
+    static_assert(P0 >= 0 && (R1 / 2) % PADG == 0 && (128 / 2) % PADG == 0, "tile origins off the gap grid");
+    static_assert(banks_ok(ROWC), "no row pitch spreads the tiles over the banks");
+    static_assert(NP >= 2 * RAD + 2, "ring too small for the stencil depth");
+};
+
 }  // namespace ss

@@ -1,5 +1,5 @@
 // 3-D stencil sweep as a structured-sparse (or dense) matrix product on
-// gfx950 matrix cores, FP32 state split into hi + lo parts as it is gathered.
+// gfx950 matrix cores, FP32 state split into hi + lo parts once per plane.
 //
 // The 3-D staircase matrix A' has one block level more than in 2-D: a patch
 // is 2r+1 z planes of the 2-D patch, and each output tile of r2 x r1 points
@@ -8,10 +8,11 @@
 // padded to whole MMA chunks, so that a chunk gathers from a single input
 // plane.  A work item is a 256 x WGH column of the grid over ZC planes; the
 // workgroup streams the input planes through a ring of LDS slabs filled by
-// LDS DMA several planes ahead.  Each input plane is gathered into B
-// registers once and multiplied by the A blocks of all 2r+1 plane offsets,
-// accumulating into the 2r+1 output planes it contributes to; the oldest of
-// those is complete after the plane and is stored.
+// LDS DMA several planes ahead.  Each input plane, once landed, is converted
+// into hi and lo word pairs (the 2-D kernels' bank-spread converted layout),
+// gathered into B registers once and multiplied by the A blocks of all 2r+1
+// plane offsets, accumulating into the 2r+1 output planes it contributes
+// to; the oldest of those is complete after the plane and is stored.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -20,7 +21,7 @@
 
 namespace ss {
 
-template <int R1, int R2, int RAD, bool VEC>
+template <int R1, int R2, int RAD, bool VEC, int NPR = Mma3Geom<R1, R2, RAD>::NP>
 struct Pipe3 {
     using G = Mma3Geom<R1, R2, RAD>;
     static constexpr int DRW = (G::SROWS + kWaves - 1) / kWaves;   // rows each wave loads per plane
@@ -39,10 +40,10 @@ struct Pipe3 {
     // From step A + NP - 2 on that is exact (WS); before it fewer stores
     // follow, and waiting for WL (no stores) waits for a few more loads than
     // needed.  Plane 0 is waited for before the first step (W0).
-    static constexpr int W0 = (G::NP - 2) * D;
-    static constexpr int WL = (G::NP - 3) * D;
-    static constexpr int WS = (G::NP - 3) * D + (G::NP - 2) * M;
-    static constexpr int STEADY = A + G::NP - 2;
+    static constexpr int W0 = (NPR - 2) * D;
+    static constexpr int WL = (NPR - 3) * D;
+    static constexpr int WS = (NPR - 3) * D + (NPR - 2) * M;
+    static constexpr int STEADY = A + NPR - 2;
 };
 
 // Issue the transfers of input plane z (already wrapped; outside the grid
@@ -103,15 +104,27 @@ __device__ inline int plane_off(const unsigned (&o2)[VPK / 2], int v, int l) {
     return (v & 1) ? (int)(w >> 16) : (int)(w & 0xffffu);
 }
 
+// Publish the workgroup's LDS writes to all its waves: wait for this
+// wave's (lgkmcnt(0), VMEM transfers left in flight), then barrier; the
+// empty asm statements keep the compiler from moving LDS accesses across.
+__device__ inline void lds_publish() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // The band of a fused zero-halo launch of two radius-1 sweeps (composed
 // into one radius-2 stencil): applied to the zero-padded grid, the composed
 // stencil is exact only at points at least one away from every face (paper
 // Section 4.1 fuses sweeps; recomputing the band keeps the zero-halo result
 // exact).  The band is cut into boxes one point thick: the first and last
-// planes in 8 x 64 (rows x columns) tiles; the first and last rows of the
-// planes between in 8 x 64 (planes x columns) tiles; the first and last
-// columns of the rows between in 8 x 64 (planes x rows) tiles.
-constexpr int kBandT = 8, kBandW = 64;
+// planes in 32 x 64 (rows x columns) tiles; the first and last rows of the
+// planes between in 32 x 64 (planes x columns) tiles; the first and last
+// columns of the rows between in 32 x 64 (planes x rows) tiles.
+constexpr int kBandT = 32, kBandW = 64;
+// LDS of a box's windows (floats) and window values a thread loads
+constexpr int kBandWin = 12288, kBandMid = 6912, kBandRegs = 24;
 
 struct BandBox {
     int z0, y0, x0, ez, ey, ex;
@@ -167,11 +180,11 @@ struct BandWin {
     static constexpr int MY = EY + 2, MX = EX + 2, NM = (EZ + 2) * MY * MX;
     static constexpr int NO = EZ * EY * EX;
     static constexpr int NR = (NW + kThreads - 1) / kThreads;     // window values per thread
-    static_assert(NW <= 4096 && NM <= 2048 && NO <= kThreads && NR <= 8, "band windows");
+    static_assert(NW <= kBandWin && NM <= kBandMid && NR <= kBandRegs, "band windows");
 };
 
 template <int EZ, int EY, int EX>
-__device__ inline void band_load(const MmaJob &g, const BandBox &bx, float (&v)[8]) {
+__device__ inline void band_load(const MmaJob &g, const BandBox &bx, float (&v)[kBandRegs]) {
     using B = BandWin<EZ, EY, EX>;
     const float *in = static_cast<const float *>(g.in);
 #pragma unroll
@@ -185,19 +198,19 @@ __device__ inline void band_load(const MmaJob &g, const BandBox &bx, float (&v)[
 }
 
 template <int EZ, int EY, int EX>
-__device__ inline void band_compute(const MmaJob &g, const BandBox &bx, const float (&v)[8], const float (&w)[27],
+__device__ inline void band_compute(const MmaJob &g, const BandBox &bx, const float (&v)[kBandRegs], const float (&w)[27],
                                     float *lds) {
     using B = BandWin<EZ, EY, EX>;
-    float *win = lds, *mid = lds + 4096;
+    float *win = lds, *mid = lds + kBandWin;
 #pragma unroll
     for (int r = 0; r < B::NR; ++r)
         if (threadIdx.x + r * kThreads < B::NW) win[threadIdx.x + r * kThreads] = v[r];
-    __syncthreads();
+    lds_publish();
     // first-sweep values: threads take them with the window's thin axis
     // slowest, so that a wave's values outside the grid (a whole layer of
     // the thin axis) are skipped together
     constexpr int MZ = EZ + 2;
-#pragma unroll
+#pragma unroll 1
     for (int r = 0; r < (B::NM + kThreads - 1) / kThreads; ++r) {
         const int i = threadIdx.x + r * kThreads;
         if (i < B::NM) {
@@ -227,23 +240,26 @@ __device__ inline void band_compute(const MmaJob &g, const BandBox &bx, const fl
             mid[(l * B::MY + j) * B::MX + k] = m;
         }
     }
-    __syncthreads();
-    const int i = threadIdx.x;
-    const int k = i % EX, j = (i / EX) % EY, l = i / (EX * EY);
-    if (i < B::NO && l < bx.ez && j < bx.ey && k < bx.ex) {
-        float acc = 0.f;
+    lds_publish();
+#pragma unroll 1
+    for (int r = 0; r < (B::NO + kThreads - 1) / kThreads; ++r) {
+        const int i = threadIdx.x + r * kThreads;
+        const int k = i % EX, j = (i / EX) % EY, l = i / (EX * EY);
+        if (i < B::NO && l < bx.ez && j < bx.ey && k < bx.ex) {
+            float acc = 0.f;
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz)
+            for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
+                for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
-                    acc = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx], mid[((l + dz) * B::MY + j + dy) * B::MX + k + dx],
-                                         acc);
-        static_cast<float *>(g.out)[((size_t)(bx.z0 + l) * g.ny + bx.y0 + j) * g.nx + bx.x0 + k] = acc;
+                    for (int dx = 0; dx < 3; ++dx)
+                        acc = __builtin_fmaf(w[(dz * 3 + dy) * 3 + dx],
+                                             mid[((l + dz) * B::MY + j + dy) * B::MX + k + dx], acc);
+            static_cast<float *>(g.out)[((size_t)(bx.z0 + l) * g.ny + bx.y0 + j) * g.nx + bx.x0 + k] = acc;
+        }
     }
     // the next box reuses the windows
-    __syncthreads();
+    lds_publish();
 }
 
 // This workgroup's boxes of one kind (tiles first, first + nb, ... below
@@ -253,7 +269,7 @@ template <int EZ, int EY, int EX>
 __device__ inline void band_kind(const MmaJob &g, const BandTiles3 &bt, int first, int end, int nb,
                                  const float (&w)[27], float *lds) {
     if (first >= end) return;
-    float v[8], nv[8];
+    float v[kBandRegs], nv[kBandRegs];
     BandBox bx = bt.box(first, g.nz, g.ny, g.nx);
     band_load<EZ, EY, EX>(g, bx, v);
     for (int t = first; t < end; t += nb) {
@@ -264,7 +280,7 @@ __device__ inline void band_kind(const MmaJob &g, const BandTiles3 &bt, int firs
         }
         band_compute<EZ, EY, EX>(g, cur, v, w, lds);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) v[r] = nv[r];
+        for (int r = 0; r < kBandRegs; ++r) v[r] = nv[r];
     }
 }
 
@@ -308,15 +324,19 @@ __device__ inline void unroll_steps(F &f, int l0, int n) {
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, bool VEC, int BC, bool BAND>
 __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     using G = Mma3Geom<R1, R2, RAD>;
-    using P = Pipe3<R1, R2, RAD, VEC>;
+    using C = Conv3Geom<R1, R2, RAD>;
+    constexpr int NP = C::NP;
+    using P = Pipe3<R1, R2, RAD, VEC, NP>;
     constexpr int MB = G::MB;
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
-    constexpr int NP = G::NP;
     constexpr int NZ = 2 * RAD + 1;          // plane offsets of the stencil
     constexpr int CPP = KC / NZ;             // K chunks per input plane
     static_assert(CPP * NZ == KC, "chunks must not straddle planes");
-    __shared__ __attribute__((aligned(16))) char lds[NP * G::PLANE_BYTES];
-    const unsigned lds0 = lds_addr_of(lds);
+    // the converted plane, then the ring of staged planes
+    __shared__ __attribute__((aligned(16))) char lds[C::CONV_BYTES + NP * G::PLANE_BYTES];
+    char *conv = lds;
+    char *ring = lds + C::CONV_BYTES;
+    const unsigned lds0 = lds_addr_of(ring);
 
     const float sigma = 1.0f / p.inv_sigma;
     const float inv_sigma = p.inv_sigma;
@@ -365,8 +385,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
     unsigned row_lds[P::DRW];
 #pragma unroll
     for (int d = 0; d < P::DRW; ++d) row_lds[d] = min(wave + d * kWaves, G::SROWS - 1) * G::CPITCH * 4;
-    // byte offset of the tile's patch origin within a slot
-    const int tbo = (srow0 * G::CPITCH + (G::HL - RAD) + nbc * 128 + tx_t * R1) * 4;
+    // byte offset of the tile's patch origin within the converted plane
+    const int tbo = (srow0 * C::ROWC + C::pos((nbc * 128 + tx_t * R1) / 2)) * 4;
 
 #pragma unroll 1
     for (int it = first; it < range_end; it += stride) {
@@ -411,41 +431,77 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                 accm[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
                 acc1[i][mb] = f4{0.f, 0.f, 0.f, 0.f};
             }
-        // B operands of two planes: the one multiplied and the next one
-        unsigned bh[2][CPP][VPK], bl[2][CPP][VPK];
-        auto gather = [&](auto buf, int l) {
-            constexpr int PB = decltype(buf)::value;
-            const char *tb = lds + (l % NP) * G::PLANE_BYTES + tbo;
+        // B operands of two planes, the one multiplied and the next one
+        // (one plane in the dense 4-byte-row variants, which gather after
+        // the products for want of registers)
+        constexpr int NB = (VEC || MODE == kSparse) ? 2 : 1;
+        unsigned bh[NB][CPP][VPK], bl[NB][CPP][VPK];
+        // staged plane l -> the converted plane: every pair split once into
+        // its hi and lo words (all reads of a thread first, then its writes)
+        auto convert = [&](int l) {
+            constexpr int NPR = G::SROWS * C::NPAIR;
+            constexpr int PER = (NPR + kThreads - 1) / kThreads;
+            // pairs read before they are split and written (one at a time in the
+            // 4-byte-row variants, whose stores take more registers)
+            constexpr int BATCH = VEC ? 3 : 1;
+            const float *st = reinterpret_cast<const float *>(ring + (l % NP) * G::PLANE_BYTES);
 #pragma unroll
-            for (int c = 0; c < CPP; ++c) {
-                float x[VPK][2];
+            for (int r0 = 0; r0 < PER; r0 += BATCH) {
+                float x[BATCH][2];
 #pragma unroll
-                for (int v = 0; v < VPK; ++v) {
-                    const float *src = reinterpret_cast<const float *>(tb + plane_off<VPK>(off2[c], v, l));
-                    x[v][0] = src[0];
-                    x[v][1] = src[1];
+                for (int r = 0; r < BATCH && r0 + r < PER; ++r) {
+                    const int i = min((int)threadIdx.x + (r0 + r) * kThreads, NPR - 1);
+                    const int row = i / C::NPAIR, j = i % C::NPAIR;
+                    x[r][0] = st[row * G::CPITCH + C::P0 + 2 * j];
+                    x[r][1] = st[row * G::CPITCH + C::P0 + 2 * j + 1];
                 }
 #pragma unroll
-                for (int v = 0; v < VPK; ++v) split2<PART>(x[v][0], x[v][1], sigma, &bh[PB][c][v], &bl[PB][c][v]);
+                for (int r = 0; r < BATCH && r0 + r < PER; ++r) {
+                    const int i = (int)threadIdx.x + (r0 + r) * kThreads;
+                    if (i < NPR) {
+                        const int row = i / C::NPAIR, j = i % C::NPAIR;
+                        unsigned h, lo;
+                        split2<PART>(x[r][0], x[r][1], sigma, &h, &lo);
+                        *reinterpret_cast<u2v *>(conv + (row * C::ROWC + C::pos(j)) * 4) = u2v{h, lo};
+                    }
+                }
             }
+        };
+        // the converted plane -> B registers: one 8-byte read per register
+        auto gather = [&](auto buf, int l) {
+            constexpr int PB = decltype(buf)::value;
+            const char *tb = conv + tbo;
+#pragma unroll
+            for (int c = 0; c < CPP; ++c)
+#pragma unroll
+                for (int v = 0; v < VPK; ++v) {
+                    const u2v w = *reinterpret_cast<const u2v *>(tb + plane_off<VPK>(off2[c], v, l));
+                    bh[PB][c][v] = w.x;
+                    bl[PB][c][v] = w.y;
+                }
         };
         wait_vmcnt<P::W0>();
         __builtin_amdgcn_s_barrier();
+        convert(0);
+        lds_publish();
         gather(std::integral_constant<int, 0>{}, 0);
         auto step = [&](auto phase, int l) {
-            constexpr int S = decltype(phase)::value;   // l % (2 * NZ)
+            constexpr int S = decltype(phase)::value;   // l % (NB * NZ)
             constexpr int R = S % NZ, PB = S % 2;
             if (l < P::STEADY) wait_vmcnt<P::WL>();
             else wait_vmcnt<P::WS>();
             // every wave's transfers of plane l + 1 have landed, and every
-            // wave is done with plane l - 1, whose slot the next issue
-            // refills
+            // wave is done with the converted plane l (gathered a step
+            // earlier) and plane l - 1's slot, which the next issue refills
             __builtin_amdgcn_s_barrier();
             issue(l + NP - 1);
-            // plane l + 1 into B registers (past the last plane this reads
-            // the repeated last plane, unused) while plane l, gathered one
-            // step earlier, is multiplied by every plane offset
-            gather(std::integral_constant<int, 1 - PB>{}, l + 1);
+            // plane l + 1 converted, then into B registers (past the last
+            // plane this reads the repeated last plane, unused), while plane
+            // l, gathered one step earlier, is multiplied by every offset
+            convert(l + 1);
+            lds_publish();
+            constexpr int CUR = PB % NB;
+            if constexpr (NB == 2) gather(std::integral_constant<int, 1 - PB>{}, l + 1);
 #pragma unroll
             for (int c = 0; c < CPP; ++c) {
 #pragma unroll
@@ -453,17 +509,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
                         const int kc = pz * CPP + c, i = (NZ - 1 - pz + R) % NZ;
-                        accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh[PB][c], accm[i][mb], aidx[mb][kc]);
-                        acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl[PB][c], acc1[i][mb], aidx[mb][kc]);
+                        accm[i][mb] = mma<MODE, PART>(ahi[mb][kc], bh[CUR][c], accm[i][mb], aidx[mb][kc]);
+                        acc1[i][mb] = mma<MODE, PART>(ahi[mb][kc], bl[CUR][c], acc1[i][mb], aidx[mb][kc]);
                     }
 #pragma unroll
                 for (int pz = 0; pz < NZ; ++pz)
 #pragma unroll
                     for (int mb = 0; mb < MB; ++mb) {
                         const int kc = pz * CPP + c, i = (NZ - 1 - pz + R) % NZ;
-                        acc1[i][mb] = mma<MODE, PART>(alo[mb][kc], bh[PB][c], acc1[i][mb], aidx[mb][kc]);
+                        acc1[i][mb] = mma<MODE, PART>(alo[mb][kc], bh[CUR][c], acc1[i][mb], aidx[mb][kc]);
                     }
             }
+            if constexpr (NB == 1) gather(std::integral_constant<int, 0>{}, l + 1);
             // output plane z0 + l - 2*RAD (slot R) is complete
             if (l >= 2 * RAD) {
                 const int zo = z0 + l - 2 * RAD;
@@ -520,7 +577,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
             }
         };
 #pragma unroll 1
-        for (int l0 = 0; l0 < nload; l0 += 2 * NZ) unroll_steps<0, 2 * NZ>(step, l0, nload);
+        // unrolled so that the accumulator rotation (and the choice of B
+        // set) is a renaming
+        for (int l0 = 0; l0 < nload; l0 += NB * NZ) unroll_steps<0, NB * NZ>(step, l0, nload);
         // the ring is refilled by the next item: let this item's transfers
         // (including the clamped ones past its last plane) land and every
         // wave finish reading first
@@ -675,7 +734,7 @@ static hipError_t launch_lds3d_bc(const MmaArgs &a, int cus, int xcds, hipStream
     MmaArgs b = a;
     b.nxcd = xcds;
     const int g = a.total_items < cus ? a.total_items : cus;
-    if constexpr (BC == kBcZero) {
+    if constexpr (BC == kBcZero && RAD >= 2) {
         if (a.edge_steps > 1) {
             hipLaunchKernelGGL((k_lds3d<RAD, VEC, BC, true>), dim3(g), dim3(kThreads), 0, s, b);
             return hipGetLastError();
@@ -690,7 +749,8 @@ static hipError_t launch3_bc(const MmaArgs &a, int cus, int xcds, hipStream_t s)
     MmaArgs b = a;
     b.nxcd = xcds;
     const int g = a.total_items < cus ? a.total_items : cus;
-    if constexpr (BC == kBcZero) {
+    // fused zero-halo launches compose radius-1 sweeps: radius 2 and up
+    if constexpr (BC == kBcZero && RAD >= 2) {
         if (a.edge_steps > 1) {
             hipLaunchKernelGGL((k_mma3d<R1, R2, KC, RAD, MODE, PART, VEC, BC, true>), dim3(g), dim3(kThreads), 0, s,
                                b);
@@ -737,7 +797,8 @@ static hipError_t launch_mma3d(MmaArgs &a, hipStream_t s) {
 
 #define SS_MMA3(R1, R2, KC, RAD, MODE, PART)                                                        \
     {{R1, R2, KC, RAD, MODE, PART, kStateF32},                                                      \
-     &launch_mma3d<R1, R2, KC, RAD, MODE, PART>, Mma3Geom<R1, R2, RAD>::WGH, Mma3Geom<R1, R2, RAD>::CPITCH}
+     &launch_mma3d<R1, R2, KC, RAD, MODE, PART>, Mma3Geom<R1, R2, RAD>::WGH, Conv3Geom<R1, R2, RAD>::ROWC, \
+     Conv3Geom<R1, R2, RAD>::PW, Conv3Geom<R1, R2, RAD>::PADG}
 
 // Radius 1 (k = 3) at tile (8,4): every plane has 60 staircase columns,
 // padded to one 64-wide sparse chunk (K 192) or two 32-wide dense chunks
@@ -763,12 +824,14 @@ MmaLaunch find_mma3d(const MmaKey &k) {
     return nullptr;
 }
 
-bool mma3d_geometry(const MmaKey &k, int *wgh, int *row) {
+bool mma3d_geometry(const MmaKey &k, int *wgh, int *row, int *pw, int *padg) {
     for (const MmaEntry &e : kTable3)
         if (e.key.r1 == k.r1 && e.key.r2 == k.r2 && e.key.kc == k.kc && e.key.rad == k.rad &&
             e.key.mode == k.mode && e.key.part == k.part) {
             *wgh = e.wgh;
             *row = e.row;
+            *pw = e.pw;
+            *padg = e.padg;
             return true;
         }
     return false;

@@ -404,7 +404,7 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
         }
         const std::vector<int> one = mode == kSparse ? compact_groups(g2, u, group_pairs(matrix_pairs(g2), 64), 64)
                                                      : dense_order(g2, u, 32);
-        if (mode == kSparse && !pairs_adjacent(g2, one)) continue;
+        if (!pair_aligned(g2, one)) continue;
         if ((int)one.size() != (mode == kSparse ? 64 : 32) * cpp) continue;
         kperm.clear();
         for (int pz = 0; pz < p->k; ++pz)
@@ -432,13 +432,13 @@ ss_status plan_mma3d(ss_plan_ *p, int engine) {
     mp.kfrag = 64;
     const ModelRow r = model_time(mp, key->r1, key->r2);
     p->model.assign({(double)r.r1, (double)r.r2, r.t, r.t_compute, r.t_global, r.t_shared, (double)r.k_pad});
-    int wgh, pitch;
-    if (!mma3d_geometry(*key, &wgh, &pitch)) return SS_E_UNSUPPORTED;
+    int wgh, pitch, pw, padg;
+    if (!mma3d_geometry(*key, &wgh, &pitch, &pw, &padg)) return SS_E_UNSUPPORTED;
     std::vector<uint8_t> blob;
     size_t o_hi, o_lo, o_mid, o_idx, o_boff, o_zero;
     p->kperm.assign(kperm.begin(), kperm.end());
-    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, 0, 0, &blob, &o_hi, &o_lo, &o_mid, &o_idx,
-                          &o_boff, &o_zero);
+    st = build_mma_tables(p, gm, kperm, mode, part, key->kc, pitch, false, pw, padg, &blob, &o_hi, &o_lo, &o_mid,
+                          &o_idx, &o_boff, &o_zero);
     if (st != SS_OK) return st;
     st = upload(p, blob);
     if (st != SS_OK) return st;
