@@ -273,15 +273,20 @@ hipError_t launch_edge2d(EdgeArgs &a, hipStream_t s) {
 // Each point's sum runs in k_direct's order (rows, then columns, fused
 // multiply-adds; the zeros of a zero halo add nothing), so the result is
 // bit for bit that of S single-sweep launches.
-constexpr int kTbTile = 32, kTbWin = kTbTile + 2 * kTbHalo;
+// Compute units and XCDs of the current device (defined with the 2-D
+// matrix kernels' launch code).
+hipError_t device_shape(int *cus, int *xcds);
 
-template <int RAD>
+// The tile is 32 x 32, or 16 x 16 when 32 x 32 tiles would leave most
+// compute units idle.
+template <int RAD, int TILE>
 __global__ __launch_bounds__(256) void k_tb2d(DirectArgs a) {
-    __shared__ double buf[2][kTbWin * kTbWin];
+    constexpr int WIN = TILE + 2 * kTbHalo;
+    __shared__ double buf[2][WIN * WIN];
     const DirectJob &g = a.job[0];
-    const int S = a.steps, H = S * RAD, W = kTbTile + 2 * H;
-    const int ntx = (g.nx + kTbTile - 1) / kTbTile;
-    const int y0 = (int)(blockIdx.x / ntx) * kTbTile - H, x0 = (int)(blockIdx.x % ntx) * kTbTile - H;
+    const int S = a.steps, H = S * RAD, W = TILE + 2 * H;
+    const int ntx = (g.nx + TILE - 1) / TILE;
+    const int y0 = (int)(blockIdx.x / ntx) * TILE - H, x0 = (int)(blockIdx.x % ntx) * TILE - H;
     const double *in = static_cast<const double *>(g.in);
     const double *w = static_cast<const double *>(a.w);
     for (int i = threadIdx.x; i < W * W; i += 256) {
@@ -318,8 +323,8 @@ __global__ __launch_bounds__(256) void k_tb2d(DirectArgs a) {
     }
     const double *res = buf[S & 1];
     double *out = static_cast<double *>(g.out);
-    for (int i = threadIdx.x; i < kTbTile * kTbTile; i += 256) {
-        const int wy = H + i / kTbTile, wx = H + i % kTbTile;
+    for (int i = threadIdx.x; i < TILE * TILE; i += 256) {
+        const int wy = H + i / TILE, wx = H + i % TILE;
         const int gy = y0 + wy, gx = x0 + wx;
         if (gy < g.ny && gx < g.nx) out[(size_t)gy * g.nx + gx] = res[wy * W + wx];
     }
@@ -329,14 +334,25 @@ hipError_t launch_direct_tb(DirectArgs &a, hipStream_t s) {
     if (a.njobs != 1 || a.steps < 1 || a.steps * a.rx > kTbHalo || a.rx != a.ry || a.rz != 0)
         return hipErrorInvalidValue;
     const DirectJob &g = a.job[0];
-    const int blocks = ((g.nx + kTbTile - 1) / kTbTile) * ((g.ny + kTbTile - 1) / kTbTile);
+    int cus = 0, xcds = 0;
+    if (const hipError_t e = device_shape(&cus, &xcds); e != hipSuccess) return e;
+    const int big = ((g.nx + 31) / 32) * ((g.ny + 31) / 32);
+    const bool small = big < cus;
+    const int t = small ? 16 : 32;
+    const int blocks = ((g.nx + t - 1) / t) * ((g.ny + t - 1) / t);
+#define SS_TB(R)                                                                                  \
+    case R:                                                                                       \
+        if (small) hipLaunchKernelGGL((k_tb2d<R, 16>), dim3(blocks), dim3(256), 0, s, a);         \
+        else hipLaunchKernelGGL((k_tb2d<R, 32>), dim3(blocks), dim3(256), 0, s, a);              \
+        break;
     switch (a.rx) {
-        case 1: hipLaunchKernelGGL(k_tb2d<1>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_tb2d<2>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 3: hipLaunchKernelGGL(k_tb2d<3>, dim3(blocks), dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_tb2d<4>, dim3(blocks), dim3(256), 0, s, a); break;
+        SS_TB(1)
+        SS_TB(2)
+        SS_TB(3)
+        SS_TB(4)
         default: return hipErrorInvalidValue;
     }
+#undef SS_TB
     return hipGetLastError();
 }
 
