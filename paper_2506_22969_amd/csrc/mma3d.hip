@@ -118,33 +118,38 @@ __device__ inline void lds_publish() {
 // into one radius-2 stencil): applied to the zero-padded grid, the composed
 // stencil is exact only at points at least one away from every face (paper
 // Section 4.1 fuses sweeps; recomputing the band keeps the zero-halo result
-// exact).  The band is cut into boxes one point thick: the first and last
-// planes in 32 x 64 (rows x columns) tiles; the first and last rows of the
-// planes between in 32 x 64 (planes x columns) tiles; the first and last
-// columns of the rows between in 32 x 64 (planes x rows) tiles.
-constexpr int kBandT = 32, kBandW = 64;
+// exact).  Along x the band is widened to kBandX0 = 4 columns a side, the
+// work items' 16-byte store granularity, so that no item store straddles
+// it.  It is cut into boxes: the first and last planes in 32 x 64 (rows x
+// columns) tiles; the first and last rows of the planes between in 32 x 64
+// (planes x columns) tiles; the first and last four columns of the rows
+// between in 32 x 32 x 4 (planes x rows x columns) boxes.
+constexpr int kBandT = 32, kBandW = 64, kBandX0 = 4;
 // LDS of a box's windows (floats) and window values a thread loads
-constexpr int kBandWin = 12288, kBandMid = 6912, kBandRegs = 24;
+constexpr int kBandWin = 12288, kBandMid = 7168, kBandRegs = 24;
 
 struct BandBox {
     int z0, y0, x0, ez, ey, ex;
-    int kind;                    // 0: plane tile, 1: row tile, 2: column tile
+    int kind;                    // 0: plane tile, 1: row tile, 2: column box
 };
 
 struct BandTiles3 {
     int mz, my;                  // planes and rows strictly inside
-    int fz, fy, fx;              // faces of each kind: 1, or 2 if the grid is wider than 1
+    int fz, fy, fx;              // faces of each kind: 1, or 2 if the grid is wide enough
     int tz, ty, tx;              // tiles per face of each kind
+    int xl, xr;                  // column boxes: [0, xl) and [xr, nx)
     __device__ inline BandTiles3(int nz, int ny, int nx) {
         mz = max(nz - 2, 0);
         my = max(ny - 2, 0);
         fz = min(nz, 2);
         fy = min(ny, 2);
-        fx = min(nx, 2);
+        xl = min(kBandX0, nx);
+        xr = max(xl, nx - kBandX0);
+        fx = xr < nx ? 2 : 1;
         const int cx = (nx + kBandW - 1) / kBandW, czm = (mz + kBandT - 1) / kBandT;
         tz = (ny + kBandT - 1) / kBandT * cx;
         ty = czm * cx;
-        tx = czm * ((my + kBandW - 1) / kBandW);
+        tx = czm * ((my + kBandT - 1) / kBandT);
     }
     __device__ inline int count() const { return fz * tz + fy * ty + fx * tx; }
     __device__ inline BandBox box(int t, int nz, int ny, int nx) const {
@@ -161,9 +166,9 @@ struct BandTiles3 {
             return BandBox{z0, f ? ny - 1 : 0, x0, min(kBandT, mz + 1 - z0), 1, min(kBandW, nx - x0), 1};
         }
         t -= fy * ty;
-        const int f = t / tx, r = t % tx, cy = (my + kBandW - 1) / kBandW;
-        const int z0 = 1 + (r / cy) * kBandT, y0 = 1 + (r % cy) * kBandW;
-        return BandBox{z0, y0, f ? nx - 1 : 0, min(kBandT, mz + 1 - z0), min(kBandW, my + 1 - y0), 1, 2};
+        const int f = t / tx, r = t % tx, cy = (my + kBandT - 1) / kBandT;
+        const int z0 = 1 + (r / cy) * kBandT, y0 = 1 + (r % cy) * kBandT;
+        return BandBox{z0, y0, f ? xr : 0, min(kBandT, mz + 1 - z0), min(kBandT, my + 1 - y0), f ? nx - xr : xl, 2};
     }
 };
 
@@ -303,7 +308,7 @@ __device__ inline void band_share3(const MmaArgs &p, int wg, int nb, float *lds)
         const int f2 = f1 >= e1 ? f1 : f1 + (e1 - f1 + nb - 1) / nb * nb;
         band_kind<1, kBandT, kBandW>(g, bt, first, e0, nb, w, lds);
         band_kind<kBandT, 1, kBandW>(g, bt, f1, e1, nb, w, lds);
-        band_kind<kBandT, kBandW, 1>(g, bt, f2, e2, nb, w, lds);
+        band_kind<kBandT, kBandT, kBandX0>(g, bt, f2, e2, nb, w, lds);
         base += e2;
     }
 }
@@ -538,27 +543,15 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma3d(MmaArgs p) {
                     for (int i = 0; i < 4; ++i) ys[i] = accm[R][mb][i] + acc1[R][mb][i] * inv_sigma;
                     const bool row_ok =
                         gyr < rows_left && plane_ok && (!BAND || (Y0 + gyr >= bnd && Y0 + gyr < g.ny - bnd));
-                    const int xlo = BAND ? bnd : 0, xhi = BAND ? g.nx - bnd : g.nx;
+                    // the band's columns: kBandX0 a side (whole groups of
+                    // four on rows of a multiple of 4 values)
+                    const int xlo = BAND ? kBandX0 : 0, xhi = BAND ? g.nx - kBandX0 : g.nx;
                     if constexpr (VEC) {
-                        // groups of four clear of the band's columns as one
-                        // 16-byte store; a group that straddles them stores
-                        // its other values one by one, under a branch: those
-                        // stores are outside the waits' count, which only
-                        // makes a wave that issues them wait longer
                         const u4v yv = {__float_as_uint(ys[0]), __float_as_uint(ys[1]), __float_as_uint(ys[2]),
                                         __float_as_uint(ys[3])};
                         const bool whole = gx >= xlo && gx + 4 <= xhi;
                         const unsigned o4 = row_ok && whole ? (unsigned)(gyr * g.nx + gx) * 4u : kOob;
                         __builtin_amdgcn_raw_buffer_store_b128(yv, orsrc, o4, 0, 0);
-                        if constexpr (BAND) {
-                            if (row_ok && !whole && gx < g.nx) {
-#pragma unroll
-                                for (int i = 0; i < 4; ++i)
-                                    if (gx + i >= xlo && gx + i < xhi)
-                                        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(ys[i]), orsrc,
-                                                                              (unsigned)(gyr * g.nx + gx + i) * 4u, 0, 0);
-                            }
-                        }
                     } else {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) {
@@ -710,7 +703,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_lds3d(MmaArgs p) {
                 float *out = static_cast<float *>(g.out) + ((size_t)zo * g.ny + Y0) * g.nx;
                 const __amdgpu_buffer_rsrc_t orsrc = uniform_rsrc(out, rows_left * g.nx * 4);
                 // band points (fused zero halo) are left to the band pass
-                const bool col_ok = BAND ? zo >= bnd && zo < g.nz - bnd && gx >= bnd && gx < g.nx - bnd : gx < g.nx;
+                const bool col_ok =
+                    BAND ? zo >= bnd && zo < g.nz - bnd && gx >= kBandX0 && gx < g.nx - kBandX0 : gx < g.nx;
 #pragma unroll
                 for (int y = 0; y < kD3Rows; ++y) {
                     const bool row_ok = y0 + y < rows_left && (!BAND || (Y0 + y0 + y >= bnd && Y0 + y0 + y < g.ny - bnd));
