@@ -5,8 +5,8 @@ readability rather than speed:
 
 1. bounding_box / compose  -- stencil coefficients as a dense (2r+1)^d array;
    S-fold temporal fusion as the FP64 self-composition of that array
-   (Section 4.1 uses 3x temporal fusion; the composition itself is the reading
-   of this build, summed in a fixed order).
+   (Section 4.1 uses 3x temporal fusion without describing the mechanism;
+   self-composition, summed in a fixed order, is the reading taken here).
 2. morph      -- Adaptive Layout Morphing (Section 3.1): stencil flattening,
    then horizontal crush of r1 adjacent outputs of a row and vertical crush of
    r2 adjacent rows, giving the staircase coefficient matrix A' of

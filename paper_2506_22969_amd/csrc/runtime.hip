@@ -284,7 +284,7 @@ ss_status plan_mma2d(ss_plan_ *p, int engine) {
     mp.coef_bytes = 2;
     mp.passes = passes;
     mp.kfrag = 64;
-    // tiles this build has kernels for
+    // tiles with instantiated kernels
     MmaKey keys[32];
     const int nkeys = mma2d_keys(p->rad, mode, part, state, keys, 32);
     std::vector<MmaKey> cands;
