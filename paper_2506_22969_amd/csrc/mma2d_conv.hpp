@@ -61,6 +61,39 @@ struct CPipe {
     static constexpr int W = (C::NSLAB - 1) * D + (S < C::NSLAB ? S : C::NSLAB) * M;
 };
 
+// 24-bit unsigned multiplies (full-rate vector instructions; a 32-bit
+// multiply takes four passes), written out so that the compiler does not
+// widen them: a * b and a * b + c, b wave-uniform, all below 2^24.
+__device__ inline unsigned mul_u24(unsigned a, unsigned b) {
+    unsigned d;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(d) : "s"(b), "v"(a));
+    return d;
+}
+__device__ inline unsigned mad_u24(unsigned a, unsigned b, unsigned c) {
+    unsigned d;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+    return d;
+}
+
+// x / D for x < XMAX as one 24-bit multiply and a shift: M = ceil(2^S / D)
+// with M * D - 2^S small enough that the truncation never reaches the next
+// integer below XMAX.
+template <unsigned D, unsigned XMAX>
+struct DivSmall {
+    static constexpr int find_shift() {
+        for (int s = 0; s < 32; ++s) {
+            const unsigned long long m = ((1ull << s) + D - 1) / D;
+            if (m < (1ull << 24) && (XMAX - 1) * m < (1ull << 32) && (XMAX - 1) * (m * D - (1ull << s)) < (1ull << s))
+                return s;
+        }
+        return -1;
+    }
+    static constexpr int S = find_shift();
+    static_assert(S >= 0 && XMAX < (1u << 24), "no 24-bit multiplier for this divisor");
+    static constexpr unsigned M = (unsigned)(((1ull << S) + D - 1) / D);
+    static __device__ inline unsigned div(unsigned x) { return mul_u24(x, M) >> S; }
+};
+
 // Issue the LDS DMA of one work item into a staging slab: every row of the
 // slab (SPITCH values from X0 - CH) in 16-byte pieces (or 4-byte values),
 // the slab taken as one flat array so that each 64-lane transfer fills 64
@@ -77,21 +110,61 @@ __device__ inline void issue_staged(const void *zero_block, const MmaJob &g, cha
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     X0 = __builtin_amdgcn_readfirstlane(X0);
     Y0 = __builtin_amdgcn_readfirstlane(Y0);
-    const char *zeros = static_cast<const char *>(zero_block);
-    const char *in = static_cast<const char *>(g.in);
     const unsigned base = lds_addr_of(stage);
+    constexpr unsigned PER_ROW = VEC ? C::NPL * C::PIECES : C::SPITCH;   // transfers per slab row
+    constexpr unsigned TB = VEC ? 16 : 4;                                  // bytes per transfer
+    const unsigned long long plane_bytes = (unsigned long long)(unsigned)g.ny * (unsigned)g.nx * C::EB;
+    const int sy0 = Y0 - RAD, sx0 = X0 - C::CH;     // first staged row and column
+    // an item whose rows and columns all lie inside the grid (every item but
+    // those along the edges) reads at 32-bit offsets from one scalar base:
+    // no per-lane bounds, wrapping or 64-bit arithmetic, and only 24-bit
+    // multiplies (rows shorter than 16 MiB, planes together under 2 GiB)
+    const bool inside = sy0 >= 0 && sy0 + C::SROWS <= g.ny && sx0 >= 0 && sx0 + C::SPITCH <= g.nx &&
+                        (unsigned long long)C::NPL * plane_bytes < (1ull << 31) &&
+                        (unsigned)g.nx * C::EB < (1u << 24);
+    if (inside) {
+        const char *sbase = static_cast<const char *>(g.in) + ((size_t)sy0 * (unsigned)g.nx + sx0) * C::EB;
+        const unsigned row_bytes = (unsigned)g.nx * C::EB;
+        using DR = DivSmall<PER_ROW, P::D * kThreads>;
+#pragma unroll
+        for (int o = 0; o < P::D; ++o) {
+            const int e0 = (o * kWaves + wave) * 64;
+            const unsigned e = (unsigned)e0 + lane;
+            const unsigned r = DR::div(e), cp = e - mul_u24(r, PER_ROW);
+            unsigned c = cp, poff = 0;
+            if constexpr (VEC && C::NPL > 1) {       // plane: cp / PIECES, at most 2
+                const bool p1 = cp >= (unsigned)C::PIECES, p2 = C::NPL > 2 && cp >= 2u * C::PIECES;
+                c = cp - (p2 ? 2u * C::PIECES : p1 ? (unsigned)C::PIECES : 0u);
+                poff = p2 ? 2u * (unsigned)plane_bytes : p1 ? (unsigned)plane_bytes : 0u;
+            }
+            unsigned off = mad_u24(r, row_bytes, c * TB + poff);
+            // lanes past the slab fill the room after it from the slab's
+            // first piece
+            if ((o + 1) * kThreads > P::NELEM && e >= (unsigned)P::NELEM) off = 0;
+            if constexpr (VEC)
+                lds_dma16_at(sbase, off, base + e0 * 16);
+            else
+                lds_dma4_at(sbase, off, base + e0 * 4);
+        }
+        return;
+    }
+    const unsigned long long in = (unsigned long long)g.in;
+    const unsigned long long zsrc = (unsigned long long)zero_block + TB * lane;
 #pragma unroll
     for (int o = 0; o < P::D; ++o) {
         const int e0 = (o * kWaves + wave) * 64;      // first transfer of the instruction
-        const int e = e0 + lane;
-        const int per_row = VEC ? C::NPL * C::PIECES : C::SPITCH;
-        const int r = e / per_row, cp = e % per_row;
-        const int pl = VEC ? cp / C::PIECES : 0, c = VEC ? cp % C::PIECES : cp;   // plane, piece
-        const int gy = wrap<BC>(Y0 - RAD + r, g.ny);
-        const int gx = wrap<BC>(X0 - C::CH + (VEC ? c * C::CH : c), g.nx);
-        const bool ok = e < P::NELEM && (BC != kBcZero || (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx));
-        const size_t at = (size_t)pl * g.ny * g.nx + (size_t)gy * g.nx + gx;
-        const char *src = ok ? in + at * C::EB : zeros + (VEC ? 16 : 4) * lane;
+        const unsigned e = (unsigned)e0 + lane;
+        const unsigned r = e / PER_ROW, cp = e - r * PER_ROW;
+        const unsigned pl = VEC && C::NPL > 1 ? cp / C::PIECES : 0u;         // plane
+        const unsigned c = VEC && C::NPL > 1 ? cp - pl * C::PIECES : cp;      // piece (or value)
+        const int gy = wrap<BC>(sy0 + (int)r, g.ny);
+        const int gx = wrap<BC>(sx0 + (int)(VEC ? c * C::CH : c), g.nx);
+        bool ok = (o + 1) * kThreads <= P::NELEM || e < (unsigned)P::NELEM;
+        if constexpr (BC == kBcZero) ok = ok && (unsigned)gy < (unsigned)g.ny && (unsigned)gx < (unsigned)g.nx;
+        const unsigned long long at =
+            in + (C::NPL > 1 ? pl * plane_bytes : 0ull) +
+            ((unsigned long long)(unsigned)gy * (unsigned)g.nx + (unsigned)gx) * C::EB;
+        const void *src = (const void *)(ok ? at : zsrc);
         if constexpr (VEC)
             lds_dma16(src, base + e0 * 16);
         else

@@ -151,6 +151,20 @@ __device__ inline void lds_dma4(const void *src, unsigned lds_addr) {
                  : "v"(src), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
                  : "memory", "m0");
 }
+// The same transfers from a wave-uniform base plus a 32-bit per-lane byte
+// offset (the scalar-base form of the instruction).
+__device__ inline void lds_dma16_at(const void *sbase, unsigned off, unsigned lds_addr) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
+                 :
+                 : "v"(off), "s"(sbase), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
+                 : "memory", "m0");
+}
+__device__ inline void lds_dma4_at(const void *sbase, unsigned off, unsigned lds_addr) {
+    asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dword %0, %1"
+                 :
+                 : "v"(off), "s"(sbase), "s"(__builtin_amdgcn_readfirstlane(lds_addr))
+                 : "memory", "m0");
+}
 __device__ inline unsigned lds_addr_of(const void *p) {
     return (unsigned)(size_t)(const __attribute__((address_space(3))) char *)p;
 }
