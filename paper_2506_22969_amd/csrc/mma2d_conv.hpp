@@ -91,6 +91,13 @@ struct DivSmall {
     static constexpr int S = find_shift();
     static_assert(S >= 0 && XMAX < (1u << 24), "no 24-bit multiplier for this divisor");
     static constexpr unsigned M = (unsigned)(((1ull << S) + D - 1) / D);
+    // every quotient checked at compile time
+    static constexpr bool exact() {
+        for (unsigned long long x = 0; x < XMAX; ++x)
+            if (((x * M) & 0xffffffffull) >> S != x / D) return false;
+        return true;
+    }
+    static_assert(exact(), "24-bit division does not match");
     static __device__ inline unsigned div(unsigned x) { return mul_u24(x, M) >> S; }
 };
 
