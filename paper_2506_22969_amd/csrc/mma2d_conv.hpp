@@ -302,88 +302,135 @@ struct GatherAddr {
     }
 };
 
-// Exact value at band point (y, x) after S zero-halo sweeps of the radius-1
-// stencil w (FP32, fixed order): the inputs within S of the point are read
-// once from the input grid, then each sweep is evaluated on the shrinking
-// square of points it still feeds, points outside the grid held at zero.
-template <int S>
-__device__ inline float band_value(const float *in, int ny, int nx, int y, int x, const float (&w)[3][3]) {
-    constexpr int H = S, E = 2 * H + 1;
-    float cur[E][E];
-#pragma unroll
-    for (int i = 0; i < E; ++i)
-#pragma unroll
-        for (int c = 0; c < E; ++c) {
-            const int sy = y - H + i, sx = x - H + c;
-            const bool in_grid = sy >= 0 && sy < ny && sx >= 0 && sx < nx;
-            const int cy = min(max(sy, 0), ny - 1), cx = min(max(sx, 0), nx - 1);
-            const float v = in[(size_t)cy * nx + cx];
-            cur[i][c] = in_grid ? v : 0.f;
-        }
-#pragma unroll
-    for (int st = 1; st <= S; ++st) {
-        const int h = H - st;             // half width after sweep st
-        float nxt[E][E];
-#pragma unroll
-        for (int i = 0; i < E; ++i)
-#pragma unroll
-            for (int c = 0; c < E; ++c) {
-                if (i < H - h || i > H + h || c < H - h || c > H + h) continue;
-                const int sy = y - H + i, sx = x - H + c;
-                float acc = 0.f;
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) acc = __builtin_fmaf(w[dy][dx], cur[i - 1 + dy][c - 1 + dx], acc);
-                nxt[i][c] = (sy >= 0 && sy < ny && sx >= 0 && sx < nx) ? acc : 0.f;
-            }
-#pragma unroll
-        for (int i = 0; i < E; ++i)
-#pragma unroll
-            for (int c = 0; c < E; ++c)
-                if (!(i < H - h || i > H + h || c < H - h || c > H + h)) cur[i][c] = nxt[i][c];
-    }
-    return cur[H][H];
-}
-
 // The band of a fused zero-halo launch (S radius-1 sweeps composed into one;
 // paper Section 4.1 fuses three): the composed stencil applied to the
 // zero-padded grid is exact only farther than S - 1 from the edges, and the
 // products leave the points within that band (widened as BandBounds says)
-// unwritten.  Workgroup wg of nb computes, after its work items, an equal
-// share of the band points of all grids of the launch, each as S plain
-// sweeps in FP32 (band_value) from the input grid: about one point per
-// thread, so the band adds about one such evaluation to the launch's tail.
-__device__ inline void band_share(const MmaArgs &p, int wg, int nb) {
+// unwritten.  The band is cut into tiles -- its top and bottom rows in
+// pieces kBand2W wide, its side columns (of the rows between) in pieces
+// kBand2H tall -- and each tile is evaluated as S plain FP32 sweeps over
+// LDS: the inputs within S of the tile, then the values of sweep s within
+// S - s of it (zero outside the grid), then the tile's points.  Every value
+// is summed in the fixed order (rows, then columns, fused multiply-adds).
+constexpr int kBand2W = 256, kBand2H = 128;
+// LDS floats: the input window and two levels of intermediate values
+constexpr int kBand2Win = 2112, kBand2Lv = 1568, kBand2Lds = kBand2Win + 2 * kBand2Lv;
+// (S <= 3: row tiles at most 2 rows deep, side tiles at most 5 columns wide)
+static_assert(kBand2Win >= 8 * (kBand2W + 6) && kBand2Win >= (kBand2H + 6) * 11 &&
+                  kBand2Lv >= 6 * (kBand2W + 4) && kBand2Lv >= (kBand2H + 4) * 9,
+              "band tile windows");
+
+struct Band2Tiles {
+    int top, bot, L, R;          // band rows [0, top) and [bot, ny); columns [0, L) and [R, nx) between
+    int cx, cy;                  // tiles per band row range, per side column range
+    int n0, n1, n2, n3;          // top, bottom, left and right tiles
+    __device__ inline Band2Tiles(const BandBounds &bb, int ny, int nx) {
+        top = min(bb.b, ny);
+        bot = max(ny - bb.b, top);
+        L = min(bb.bl, nx);
+        R = max(bb.br, L);
+        cx = (nx + kBand2W - 1) / kBand2W;
+        cy = (bot - top + kBand2H - 1) / kBand2H;
+        n0 = top > 0 ? cx : 0;
+        n1 = bot < ny ? cx : 0;
+        n2 = L > 0 ? cy : 0;
+        n3 = R < nx ? cy : 0;
+    }
+    __device__ inline int count() const { return n0 + n1 + n2 + n3; }
+    // tile t: first row and column, rows and columns
+    __device__ inline void box(int t, int ny, int nx, int *y0, int *x0, int *h, int *w) const {
+        if (t < n0 + n1) {
+            const bool f = t >= n0;
+            const int c = f ? t - n0 : t;
+            *y0 = f ? bot : 0;
+            *h = f ? ny - bot : top;
+            *x0 = c * kBand2W;
+            *w = min(kBand2W, nx - *x0);
+        } else {
+            t -= n0 + n1;
+            const bool f = t >= n2;
+            const int c = f ? t - n2 : t;
+            *y0 = top + c * kBand2H;
+            *h = min(kBand2H, bot - *y0);
+            *x0 = f ? R : 0;
+            *w = f ? nx - R : L;
+        }
+    }
+};
+
+// Publish the workgroup's LDS writes: wait for this wave's LDS accesses
+// (transfers to global memory left in flight), then barrier; the empty asm
+// statements keep the compiler from moving LDS accesses across.
+__device__ inline void band_publish() {
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One band tile (rows y0.., columns x0.., h x w points) after S sweeps.
+template <int S>
+__device__ inline void band_tile(const MmaJob &g, int y0, int x0, int h, int w, const float (&cw)[3][3],
+                                 float *lds) {
+    const float *in = static_cast<const float *>(g.in);
+    float *out = static_cast<float *>(g.out);
+    {
+        const int W = w + 2 * S, n = (h + 2 * S) * W;
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            const int r = i / W, c = i - r * W;
+            const int gy = y0 - S + r, gx = x0 - S + c;
+            lds[i] = (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx) ? in[(size_t)gy * g.nx + gx] : 0.f;
+        }
+    }
+    band_publish();
+    const float *src = lds;
+#pragma unroll
+    for (int st = 1; st <= S; ++st) {
+        const int m = S - st;                  // sweep st's values reach m beyond the tile
+        const int W = w + 2 * m, n = (h + 2 * m) * W, SW = W + 2;
+        float *dst = lds + kBand2Win + ((st - 1) & 1) * kBand2Lv;
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            const int r = i / W, c = i - r * W;
+            float acc = 0.f;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) acc = __builtin_fmaf(cw[dy][dx], src[(r + dy) * SW + c + dx], acc);
+            const int gy = y0 - m + r, gx = x0 - m + c;
+            if (st < S)
+                dst[i] = (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx) ? acc : 0.f;
+            else
+                out[(size_t)gy * g.nx + gx] = acc;
+        }
+        band_publish();                        // (the last one: the next tile reuses the LDS)
+        src = dst;
+    }
+}
+
+// Workgroup wg of nb computes, after its work items (its LDS free), the
+// band tiles wg, wg + nb, ... of all grids of the launch (numbered over
+// the grids in order).
+__device__ inline void band_share(const MmaArgs &p, int wg, int nb, float *lds) {
     if (p.edge_steps < 2) return;
     float w[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c) w[i][c] = p.edge_w32[i * 3 + c];
-    long long total = 0;
+    int base = 0;
     for (int j = 0; j < p.njobs; ++j) {
         const MmaJob &g = p.job[j];
-        total += BandShape(band_bounds(p, g), g.ny, g.nx).count(g.ny, g.nx);
-    }
-    const long long lo = total * wg / nb, hi = total * (wg + 1) / nb;
-    for (long long idx = lo + threadIdx.x; idx < hi; idx += kThreads) {
-        long long l = idx;
-        int j = 0;
-        for (; j < p.njobs - 1; ++j) {
-            const MmaJob &g = p.job[j];
-            const long long c = BandShape(band_bounds(p, g), g.ny, g.nx).count(g.ny, g.nx);
-            if (l < c) break;
-            l -= c;
+        const Band2Tiles bt(band_bounds(p, g), g.ny, g.nx);
+        const int n = bt.count();
+        for (int t = base <= wg ? wg - base : (nb - (base - wg) % nb) % nb; t < n; t += nb) {
+            int y0, x0, h, tw;
+            bt.box(t, g.ny, g.nx, &y0, &x0, &h, &tw);
+            if (p.edge_steps == 3)
+                band_tile<3>(g, y0, x0, h, tw, w, lds);
+            else
+                band_tile<2>(g, y0, x0, h, tw, w, lds);
         }
-        const MmaJob &g = p.job[j];
-        const BandShape bs(band_bounds(p, g), g.ny, g.nx);
-        int y, x;
-        bs.point(l, g.nx, &y, &x);
-        const float *in = static_cast<const float *>(g.in);
-        const float v = p.edge_steps == 3 ? band_value<3>(in, g.ny, g.nx, y, x, w)
-                                          : band_value<2>(in, g.ny, g.nx, y, x, w);
-        static_cast<float *>(g.out)[(size_t)y * g.nx + x] = v;
+        base += n;
     }
 }
 
@@ -596,6 +643,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
     constexpr int NS = C::NSLAB;
     __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
+    static_assert(STATE != kStateF32 || C::LDS_BYTES >= 4 * kBand2Lds, "band tiles need more LDS");
     char *conv = lds;
     auto stage = [&](int i) { return lds + C::CONV_BYTES + i * C::STAGE_ALLOC; };
 
@@ -610,7 +658,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     const int total = (int)((long long)p.total_items * (before + stride) / nwg);
     const int first = range_begin + blockIdx.x / nxcd;
     if (first >= total) {
-        if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg);
+        if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
         return;
     }
 
@@ -686,7 +734,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     // the pipeline always runs NS items ahead: let those transfers land
     // before the workgroup's LDS is released
     wait_vmcnt<0>();
-    if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg);
+    if constexpr (STATE == kStateF32) {
+        __builtin_amdgcn_s_barrier();            // every wave is done with the slabs
+        band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
+    }
 }
 
 template <int R1, int R2, int KC, int RAD, int MODE, int PART, int STATE, bool VEC, int BC>

@@ -297,33 +297,4 @@ __device__ inline BandBounds band_bounds(const MmaArgs &p, const MmaJob &g) {
     return BandBounds{b, (b + 3) & ~3, max(0, (g.nx - b) & ~3)};
 }
 
-// Band points of one grid (BandBounds): the rows within b of the top and
-// bottom edges in full, then columns [0, L) and [R, nx) of the rows between.
-struct BandShape {
-    int top, bot, L, R, nrb, side;        // rows [0, top) and [bot, ny); side columns per middle row
-    __device__ inline BandShape(const BandBounds &bb, int ny, int nx) {
-        top = min(bb.b, ny);
-        bot = max(ny - bb.b, top);
-        L = min(bb.bl, nx);
-        R = max(bb.br, L);
-        nrb = top + (ny - bot);
-        side = L + (nx - R);
-    }
-    __device__ inline long long count(int ny, int nx) const {
-        return (long long)nrb * nx + (long long)(ny - nrb) * side;
-    }
-    __device__ inline void point(long long l, int nx, int *y, int *x) const {
-        if (l < (long long)nrb * nx) {
-            const int ri = (int)(l / nx);
-            *y = ri < top ? ri : bot + (ri - top);
-            *x = (int)(l % nx);
-        } else {
-            l -= (long long)nrb * nx;
-            const int c = (int)(l % side);
-            *y = top + (int)(l / side);
-            *x = c < L ? c : R + (c - L);
-        }
-    }
-};
-
 }  // namespace ss
