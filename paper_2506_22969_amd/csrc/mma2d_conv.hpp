@@ -369,21 +369,23 @@ __device__ inline void band_publish() {
 }
 
 // One band tile (rows y0.., columns x0.., h x w points) after S sweeps.
+// The input window is read from the grid into lds, or is already at lds +
+// pre (pre >= 0: staged by LDS DMA, in the same layout).
 template <int S>
 __device__ inline void band_tile(const MmaJob &g, int y0, int x0, int h, int w, const float (&cw)[3][3],
-                                 float *lds) {
+                                 float *lds, int pre) {
     const float *in = static_cast<const float *>(g.in);
     float *out = static_cast<float *>(g.out);
-    {
+    const float *src = lds + (pre >= 0 ? pre : 0);
+    if (pre < 0) {
         const int W = w + 2 * S, n = (h + 2 * S) * W;
         for (int i = threadIdx.x; i < n; i += kThreads) {
             const int r = i / W, c = i - r * W;
             const int gy = y0 - S + r, gx = x0 - S + c;
             lds[i] = (gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx) ? in[(size_t)gy * g.nx + gx] : 0.f;
         }
+        band_publish();
     }
-    band_publish();
-    const float *src = lds;
 #pragma unroll
     for (int st = 1; st <= S; ++st) {
         const int m = S - st;                  // sweep st's values reach m beyond the tile
@@ -407,10 +409,57 @@ __device__ inline void band_tile(const MmaJob &g, int y0, int x0, int h, int w, 
     }
 }
 
+// The first of the band tiles wg, wg + nb, ... (numbered over the grids of
+// the launch in order): its grid and number, or false if there is none.
+__device__ inline bool first_band_tile(const MmaArgs &p, int wg, int nb, int *jj, int *tt) {
+    int base = 0;
+    for (int j = 0; j < p.njobs; ++j) {
+        const MmaJob &g = p.job[j];
+        const int n = Band2Tiles(band_bounds(p, g), g.ny, g.nx).count();
+        const int t = base <= wg ? wg - base : (nb - (base - wg) % nb) % nb;
+        if (t < n) {
+            *jj = j;
+            *tt = t;
+            return true;
+        }
+        base += n;
+    }
+    return false;
+}
+
+// LDS DMA of a band tile's input window (rows y0 - S.., columns x0 - S..,
+// row-major, zero outside the grid) into a staging slab: the same count of
+// transfers per wave as an item's (4-byte ones: the window's rows start
+// anywhere), so that the pipeline's waits count it as one.
+template <int R1, int R2, int RAD, int STATE, bool VEC>
+__device__ inline void issue_band_window(const void *zero_block, const MmaJob &g, char *stage, int y0, int x0,
+                                         int h, int w, int S) {
+    using C = ConvGeom<R1, R2, RAD, STATE>;
+    using P = CPipe<R1, R2, RAD, STATE, VEC>;
+    static_assert(P::D * kThreads >= kBand2Win && P::D * kThreads * 4 <= C::STAGE_ALLOC, "band window transfers");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned base = lds_addr_of(stage);
+    const int W = w + 2 * S, n = (h + 2 * S) * W;
+    const float *in = static_cast<const float *>(g.in);
+    const float *zf = static_cast<const float *>(zero_block);
+#pragma unroll
+    for (int o = 0; o < P::D; ++o) {
+        const int e0 = (o * kWaves + wave) * 64;
+        const int e = e0 + lane;
+        const int r = e / W, c = e - r * W;
+        const int gy = y0 - S + r, gx = x0 - S + c;
+        const bool ok = e < n && gy >= 0 && gy < g.ny && gx >= 0 && gx < g.nx;
+        lds_dma4(ok ? static_cast<const void *>(in + (size_t)gy * g.nx + gx) : static_cast<const void *>(zf + lane),
+                 base + e0 * 4);
+    }
+}
+
 // Workgroup wg of nb computes, after its work items (its LDS free), the
 // band tiles wg, wg + nb, ... of all grids of the launch (numbered over
-// the grids in order).
-__device__ inline void band_share(const MmaArgs &p, int wg, int nb, float *lds) {
+// the grids in order); the first one's window may already be staged at
+// lds + pre (pre >= 0).
+__device__ inline void band_share(const MmaArgs &p, int wg, int nb, float *lds, int pre) {
     if (p.edge_steps < 2) return;
     float w[3][3];
 #pragma unroll
@@ -426,9 +475,10 @@ __device__ inline void band_share(const MmaArgs &p, int wg, int nb, float *lds) 
             int y0, x0, h, tw;
             bt.box(t, g.ny, g.nx, &y0, &x0, &h, &tw);
             if (p.edge_steps == 3)
-                band_tile<3>(g, y0, x0, h, tw, w, lds);
+                band_tile<3>(g, y0, x0, h, tw, w, lds, pre);
             else
-                band_tile<2>(g, y0, x0, h, tw, w, lds);
+                band_tile<2>(g, y0, x0, h, tw, w, lds, pre);
+            pre = -1;
         }
         base += n;
     }
@@ -643,7 +693,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     constexpr int VPK = (MODE == kSparse) ? 8 : 4;
     constexpr int NS = C::NSLAB;
     __shared__ __attribute__((aligned(16))) char lds[C::LDS_BYTES];
-    static_assert(STATE != kStateF32 || C::LDS_BYTES >= 4 * kBand2Lds, "band tiles need more LDS");
+    static_assert(STATE != kStateF32 || C::CONV_BYTES >= 4 * kBand2Lds, "band tiles need more LDS");
     char *conv = lds;
     auto stage = [&](int i) { return lds + C::CONV_BYTES + i * C::STAGE_ALLOC; };
 
@@ -658,7 +708,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     const int total = (int)((long long)p.total_items * (before + stride) / nwg);
     const int first = range_begin + blockIdx.x / nxcd;
     if (first >= total) {
-        if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
+        if constexpr (STATE == kStateF32) band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds), -1);
         return;
     }
 
@@ -702,7 +752,25 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
         X0 = (local % nbands) * kBandX;
         Y0 = (local / nbands) * G::WGH;
     };
+    // the first transfer round past this workgroup's last item stages the
+    // window of its first band tile instead (fused zero-halo launches), so
+    // that the band pass after the items starts with its inputs in LDS
+    // (round n_items: the first past the last item)
+    const int n_items = (total - first + stride - 1) / stride;
+    int band_j = -1, band_t = 0;
+    if constexpr (STATE == kStateF32)
+        if (p.edge_steps < 2 || !first_band_tile(p, blockIdx.x, nwg, &band_j, &band_t)) band_j = -1;
     auto issue = [&](int s) {
+        if constexpr (STATE == kStateF32) {
+            if (band_j >= 0 && s == n_items) {
+                const MmaJob g = p.job[band_j];
+                int y0, x0, h, tw;
+                Band2Tiles(band_bounds(p, g), g.ny, g.nx).box(band_t, g.ny, g.nx, &y0, &x0, &h, &tw);
+                issue_band_window<R1, R2, RAD, STATE, VEC>(p.zeros, g, stage(s % NS), y0, x0, h, tw,
+                                                           p.edge_steps);
+                return;
+            }
+        }
         int j, X0, Y0;
         locate(item(s), j, X0, Y0);
         const MmaJob g = p.job[j];
@@ -736,7 +804,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_mma2c(MmaArgs p) {
     wait_vmcnt<0>();
     if constexpr (STATE == kStateF32) {
         __builtin_amdgcn_s_barrier();            // every wave is done with the slabs
-        band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds));
+        band_share(p, blockIdx.x, nwg, reinterpret_cast<float *>(lds),
+                   band_j >= 0 ? (C::CONV_BYTES + (n_items % NS) * C::STAGE_ALLOC) / 4 : -1);
     }
 }
 
